@@ -1,0 +1,306 @@
+"""Pins for the CPU oracle: checks against facts the mathematics fixes, none of
+which re-types the oracle's own formulas.
+
+Each ``pin_*`` takes an oracle module ``O`` (the real one, or one with a
+planted mistake) and raises ``AssertionError`` when the oracle disagrees with
+the fact.  The real oracle must pass all of them; every planted mistake must
+fail at least one (see ``test_oracle_mutants.py``).
+
+Facts used (derivations are in the docstrings):
+* brute force: pure-Python loops over the 4-index integrals, written from the
+  paper's printed index forms (Eq. MP2_ints and the Appendix definitions of
+  X, Gamma, D_ij and D_ab), on tiny inputs;
+* a closed form for nocc = nvir = 1;
+* equal orbital energies, where E reduces to Gram-matrix traces;
+* dE/dB = 4 Gamma (the factor of the Appendix's Z = 4 Gamma + ...), checked by
+  complex-step differentiation;
+* dE/d eps_i = 2 (P_ij)_ii and dE/d eps_a = 2 (P_ab)_aa, complex step;
+* symmetry, trace and sign properties, orthogonal rotation of the auxiliary
+  index, global shift of all orbital energies, scaling of B, zero padding and
+  index permutation.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+RTOL = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = max(np.max(np.abs(b)), 1e-300)
+    return float(np.max(np.abs(a - b)) / den)
+
+
+def tiny_inputs(nocc, nvir, naux, seed, complex_ok=False):
+    rng = np.random.default_rng(seed)
+    B = 0.3 * rng.standard_normal((nocc, nvir, naux)) * np.exp(-np.arange(naux) / 7.0)
+    eo = np.sort(rng.uniform(-20.0, -0.3, nocc))
+    ev = np.sort(rng.uniform(0.1, 5.0, nvir))
+    return B, eo, ev
+
+
+def brute_force(B, eo, ev):
+    """All outputs from pure-Python loops over the paper's index forms."""
+    nocc, nvir, naux = B.shape
+    I = {}
+    for i in range(nocc):
+        for a in range(nvir):
+            for j in range(nocc):
+                for b in range(nvir):
+                    s = 0.0
+                    for P in range(naux):
+                        s += B[i, a, P] * B[j, b, P]
+                    I[i, a, j, b] = s
+
+    def D(i, j, a, b):
+        return eo[i] + eo[j] - ev[a] - ev[b]
+
+    X = {(i, j, a, b): I[i, a, j, b] / D(i, j, a, b)
+         for i in range(nocc) for j in range(nocc) for a in range(nvir) for b in range(nvir)}
+    E = 0.0
+    e_pair = np.zeros((nocc, nocc))
+    for i in range(nocc):
+        for j in range(nocc):
+            s = 0.0
+            for a in range(nvir):
+                for b in range(nvir):
+                    s += I[i, a, j, b] * (2 * I[i, a, j, b] - I[i, b, j, a]) / D(i, j, a, b)
+            e_pair[i, j] = s
+            E += s
+    G = np.zeros((nocc, nvir, naux))
+    for i in range(nocc):
+        for a in range(nvir):
+            for P in range(naux):
+                s = 0.0
+                for j in range(nocc):
+                    for b in range(nvir):
+                        s += (2 * X[i, j, a, b] - X[i, j, b, a]) * B[j, b, P]
+                G[i, a, P] = s
+    Pij = np.zeros((nocc, nocc))
+    for i in range(nocc):
+        for j in range(nocc):
+            s = 0.0
+            for a in range(nvir):
+                for b in range(nvir):
+                    for k in range(nocc):
+                        s += (2 * X[i, k, a, b] - X[k, i, a, b]) * X[j, k, a, b]
+            Pij[i, j] = -s
+    Pab = np.zeros((nvir, nvir))
+    for a in range(nvir):
+        for b in range(nvir):
+            s = 0.0
+            for i in range(nocc):
+                for j in range(nocc):
+                    for c in range(nvir):
+                        s += (2 * X[i, j, a, c] - X[i, j, c, a]) * X[i, j, b, c]
+            Pab[a, b] = s
+    return dict(E=E, e_pair=e_pair, Gamma=G, P_ij=Pij, P_ab=Pab)
+
+
+def pin_brute_force(O, shapes=((2, 3, 4), (3, 4, 5), (1, 5, 3), (4, 2, 6))):
+    for n, (nocc, nvir, naux) in enumerate(shapes):
+        B, eo, ev = tiny_inputs(nocc, nvir, naux, 10 + n)
+        r = O.fragment(B, eo, ev)
+        bf = brute_force(B, eo, ev)
+        assert abs(r["E"] - bf["E"]) <= 1e-13 * abs(bf["E"]), ("E", r["E"], bf["E"])
+        for key in ("e_pair", "Gamma", "P_ij", "P_ab"):
+            assert rel(r[key], bf[key]) <= 1e-13, (key, rel(r[key], bf[key]))
+
+
+def pin_closed_form_single_pair(O):
+    """nocc = nvir = 1: V = sum_P B_P^2, D = 2(eps_i - eps_a), X = V / D,
+    T = 2X - X = X, so E = V^2 / D, Gamma_P = X B_P, P_ij = -X^2, P_ab = X^2."""
+    rng = np.random.default_rng(3)
+    for naux in (1, 2, 7):
+        Bv = rng.standard_normal(naux)
+        ei, ea = -1.3, 0.7
+        r = O.fragment(Bv.reshape(1, 1, naux), np.array([ei]), np.array([ea]))
+        V = float(np.dot(Bv, Bv))
+        D = 2.0 * (ei - ea)
+        X = V / D
+        assert abs(r["E"] - V * V / D) <= 1e-14 * abs(V * V / D)
+        assert rel(r["Gamma"].ravel(), X * Bv) <= 1e-14
+        assert abs(r["P_ij"][0, 0] + X * X) <= 1e-14 * X * X
+        assert abs(r["P_ab"][0, 0] - X * X) <= 1e-14 * X * X
+
+
+def pin_equal_energies(O):
+    """All eps_i = e_o and all eps_a = e_v: every D equals 2(e_o - e_v), so
+    E = [2 sum (ia|jb)^2 - sum (ia|jb)(ib|ja)] / (2(e_o - e_v)).  With the
+    matrix M[(i,a), P] = B^P_ia and G = M^T M (naux x naux Gram matrix),
+    sum (ia|jb)^2 = tr(G^2); with W_ij = B_i^T B_j (naux x naux, a contraction
+    over the orbital index first instead of the auxiliary index) and
+    W_ji = W_ij^T, the exchange sum is sum_ij sum_PQ W_ij[P,Q] W_ji[P,Q] =
+    sum_ij tr(W_ij W_ij)."""
+    for nocc, nvir, naux in ((3, 4, 5), (2, 7, 3)):
+        B, _, _ = tiny_inputs(nocc, nvir, naux, 21 + nocc)
+        eo_v, ev_v = -2.5, 1.25
+        eo = np.full(nocc, eo_v)
+        ev = np.full(nvir, ev_v)
+        M = B.reshape(nocc * nvir, naux)
+        G = M.T @ M
+        coul = np.trace(G @ G)
+        exch = 0.0
+        for i in range(nocc):
+            for j in range(nocc):
+                W = B[i].T @ B[j]
+                exch += np.trace(W @ W)
+        E_ref = (2.0 * coul - exch) / (2.0 * (eo_v - ev_v))
+        r = O.fragment(B, eo, ev)
+        assert abs(r["E"] - E_ref) <= 1e-13 * abs(E_ref), (r["E"], E_ref)
+
+
+def _complex_E(O, B, eo, ev):
+    return O.fragment(B, eo, ev, gamma=False, density=False)["E"]
+
+
+def pin_dE_dB_is_4_gamma(O):
+    """dE/dB^P_ia = 4 Gamma^P_ia, every element, by complex step (h = 1e-30):
+    Im E(B + i h e_n) / h equals the derivative to rounding."""
+    h = 1e-30
+    for nocc, nvir, naux in ((2, 3, 3), (3, 2, 4)):
+        B, eo, ev = tiny_inputs(nocc, nvir, naux, 31 + naux)
+        G = O.fragment(B, eo, ev)["Gamma"]
+        dE = np.zeros_like(B)
+        for idx in np.ndindex(B.shape):
+            Bc = B.astype(np.complex128)
+            Bc[idx] += 1j * h
+            dE[idx] = _complex_E(O, Bc, eo, ev).imag / h
+        assert rel(dE, 4.0 * G) <= 1e-12, rel(dE, 4.0 * G)
+
+
+def pin_dE_deps_is_2_diagP(O):
+    """dE/d eps_i = 2 (P_ij)_ii and dE/d eps_a = 2 (P_ab)_aa (complex step)."""
+    h = 1e-30
+    B, eo, ev = tiny_inputs(3, 4, 5, 41)
+    r = O.fragment(B, eo, ev)
+    for i in range(len(eo)):
+        e = eo.astype(np.complex128)
+        e[i] += 1j * h
+        d = _complex_E(O, B, e, ev).imag / h
+        assert abs(d - 2.0 * r["P_ij"][i, i]) <= 1e-12 * abs(d), (i, d, r["P_ij"][i, i])
+    for a in range(len(ev)):
+        e = ev.astype(np.complex128)
+        e[a] += 1j * h
+        d = _complex_E(O, B, eo, e).imag / h
+        assert abs(d - 2.0 * r["P_ab"][a, a]) <= 1e-12 * abs(d), (a, d, r["P_ab"][a, a])
+
+
+def pin_symmetry_and_sign(O):
+    """e_ij = e_ji <= 0 (with W = 1/|D| symmetric in a, b,
+    sum W V V^T <= sum W V^2 by Cauchy-Schwarz), E <= 0, P_ij and P_ab
+    symmetric, tr P_ij + tr P_ab = 0, tr P_ab >= 0."""
+    B, eo, ev = tiny_inputs(5, 6, 8, 51)
+    r = O.fragment(B, eo, ev)
+    ep = r["e_pair"]
+    assert rel(ep, ep.T) <= 1e-13
+    assert np.all(ep <= 0.0) and r["E"] <= 0.0
+    assert rel(r["P_ij"], r["P_ij"].T) <= 1e-13
+    assert rel(r["P_ab"], r["P_ab"].T) <= 1e-13
+    tij, tab = np.trace(r["P_ij"]), np.trace(r["P_ab"])
+    assert tab >= 0.0
+    assert abs(tij + tab) <= 1e-13 * abs(tab)
+
+
+def pin_aux_rotation(O):
+    """B^P -> sum_Q O_PQ B^Q with O orthogonal: (ia|jb) is unchanged, so E,
+    e_ij, P_ij, P_ab are invariant and Gamma rotates the same way."""
+    B, eo, ev = tiny_inputs(4, 5, 6, 61)
+    Q, _ = np.linalg.qr(np.random.default_rng(62).standard_normal((6, 6)))
+    r0 = O.fragment(B, eo, ev)
+    r1 = O.fragment(B @ Q, eo, ev)
+    assert abs(r1["E"] - r0["E"]) <= 1e-13 * abs(r0["E"])
+    for key in ("e_pair", "P_ij", "P_ab"):
+        assert rel(r1[key], r0[key]) <= 1e-12, key
+    assert rel(r1["Gamma"], r0["Gamma"] @ Q) <= 1e-12
+
+
+def pin_global_shift(O):
+    """eps -> eps + c for occupied and virtual alike leaves every denominator,
+    hence every output, unchanged (c chosen so the shift is exact)."""
+    B, eo, ev = tiny_inputs(3, 4, 5, 71)
+    eo = np.round(eo * 64) / 64
+    ev = np.round(ev * 64) / 64
+    r0 = O.fragment(B, eo, ev)
+    r1 = O.fragment(B, eo + 4.0, ev + 4.0)
+    for key in ("e_pair", "Gamma", "P_ij", "P_ab"):
+        assert np.array_equal(r0[key], r1[key]), key
+
+
+def pin_scaling(O):
+    """B -> s B: V scales by s^2, so E and P scale by s^4 and Gamma by s^3."""
+    B, eo, ev = tiny_inputs(3, 4, 5, 81)
+    s = 2.0
+    r0 = O.fragment(B, eo, ev)
+    r1 = O.fragment(s * B, eo, ev)
+    assert abs(r1["E"] - s ** 4 * r0["E"]) <= 1e-14 * abs(r1["E"])
+    assert rel(r1["Gamma"], s ** 3 * r0["Gamma"]) <= 1e-14
+    assert rel(r1["P_ij"], s ** 4 * r0["P_ij"]) <= 1e-14
+    assert rel(r1["P_ab"], s ** 4 * r0["P_ab"]) <= 1e-14
+
+
+def pin_zero_padding(O):
+    """Extra auxiliary functions, virtuals or occupied orbitals whose B is
+    zero contribute nothing: E unchanged, padded outputs zero."""
+    B, eo, ev = tiny_inputs(3, 4, 5, 91)
+    r0 = O.fragment(B, eo, ev)
+    Ba = np.concatenate([B, np.zeros((3, 4, 2))], axis=2)
+    ra = O.fragment(Ba, eo, ev)
+    assert ra["E"] == r0["E"] and rel(ra["Gamma"][:, :, :5], r0["Gamma"]) <= 1e-15
+    assert np.all(ra["Gamma"][:, :, 5:] == 0)
+    Bv = np.concatenate([B, np.zeros((3, 2, 5))], axis=1)
+    rv = O.fragment(Bv, eo, np.concatenate([ev, [6.0, 7.5]]))
+    assert abs(rv["E"] - r0["E"]) <= 1e-15 * abs(r0["E"])
+    assert rel(rv["P_ab"][:4, :4], r0["P_ab"]) <= 1e-14 and np.all(rv["P_ab"][4:, :] == 0)
+    Bo = np.concatenate([np.zeros((1, 4, 5)), B], axis=0)
+    ro = O.fragment(Bo, np.concatenate([[-30.0], eo]), ev)
+    assert abs(ro["E"] - r0["E"]) <= 1e-15 * abs(r0["E"])
+    assert rel(ro["P_ij"][1:, 1:], r0["P_ij"]) <= 1e-14 and np.all(ro["P_ij"][0, :] == 0)
+
+
+def pin_permutation(O):
+    """Relabelling occupied (or virtual) orbitals together with their
+    energies permutes the outputs the same way."""
+    B, eo, ev = tiny_inputs(4, 5, 3, 101)
+    r0 = O.fragment(B, eo, ev)
+    po = np.array([2, 0, 3, 1])
+    pv = np.array([4, 1, 0, 3, 2])
+    r1 = O.fragment(B[po][:, pv], eo[po], ev[pv])
+    assert rel(r1["e_pair"], r0["e_pair"][np.ix_(po, po)]) <= 1e-13
+    assert rel(r1["Gamma"], r0["Gamma"][po][:, pv]) <= 1e-13
+    assert rel(r1["P_ij"], r0["P_ij"][np.ix_(po, po)]) <= 1e-13
+    assert rel(r1["P_ab"], r0["P_ab"][np.ix_(pv, pv)]) <= 1e-13
+
+
+def pin_sampled_entry_points(O):
+    """The single-output functions (pair_energy, gamma_row, p_ab_element,
+    p_ij_element) agree with brute force."""
+    B, eo, ev = tiny_inputs(3, 4, 5, 111)
+    bf = brute_force(B, eo, ev)
+    for i in range(3):
+        for j in range(3):
+            assert abs(O.pair_energy(B, eo, ev, i, j) - bf["e_pair"][i, j]) <= 1e-13 * abs(bf["e_pair"][i, j])
+            assert abs(O.p_ij_element(B, eo, ev, i, j) - bf["P_ij"][i, j]) <= 1e-12 * abs(bf["P_ij"]).max()
+    for i in range(3):
+        for a in range(4):
+            assert rel(O.gamma_row(B, eo, ev, i, a), bf["Gamma"][i, a]) <= 1e-12
+    for a in range(4):
+        for b in range(4):
+            assert abs(O.p_ab_element(B, eo, ev, a, b) - bf["P_ab"][a, b]) <= 1e-12 * abs(bf["P_ab"]).max()
+
+
+def pin_exact_sum(O):
+    """E_hi + E_lo is the exact sum: values whose float sum loses digits."""
+    vals = np.array([1e16, 1.0, -1e16, 3.0, 1e-3])
+    hi, lo = O.exact_sum(vals)
+    assert hi == 4.001 and abs(lo) < 1e-15
+    vals = np.array([2.0 ** 60, 1.0, 1.0])
+    hi, lo = O.exact_sum(vals)
+    assert hi == 2.0 ** 60 and lo == 2.0
+
+
+ALL_PINS = [pin_brute_force, pin_closed_form_single_pair, pin_equal_energies, pin_dE_dB_is_4_gamma,
+            pin_dE_deps_is_2_diagP, pin_symmetry_and_sign, pin_aux_rotation, pin_global_shift,
+            pin_scaling, pin_zero_padding, pin_permutation, pin_sampled_entry_points, pin_exact_sum]

@@ -1,0 +1,20 @@
+"""The CPU oracle against facts fixed by the paper and by the mathematics.
+
+Pin status of every oracle function:
+  pair_integrals, denominators, amplitudes, combination, pair_quantities,
+  fragment (all outputs)      brute force, closed form, equal energies,
+                              dE/dB = 4 Gamma, dE/d eps = 2 diag P, invariants
+  pair_energy, gamma_row, p_ab_element, p_ij_element
+                              brute force
+  exact_sum                   exact cancellation cases
+No function is unpinned.
+"""
+import pytest
+
+from oracle import rimp2_oracle as O
+import pins
+
+
+@pytest.mark.parametrize("pin", pins.ALL_PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin(O)
