@@ -1,0 +1,183 @@
+/*
+ * rimp2.h -- C ABI of the MI355X (gfx950) closed-shell RI-MP2 fragment kernel.
+ *
+ * What is computed (arXiv 2410.21888; restricted closed shell, no frozen core,
+ * Sec. "Background"):
+ *
+ *   (ia|jb) = sum_P B^P_ia B^P_jb                       (Eq. MP2_ints)
+ *   X_ij^ab = (ia|jb) / (eps_i + eps_j - eps_a - eps_b)  (Appendix, amplitudes)
+ *   T_ij^ab = 2 X_ij^ab - X_ij^ba
+ *   e_ij    = sum_ab T_ij^ab (ia|jb),  E = sum_ij e_ij   (RI-MP2 fragment energy
+ *                                                         of Eq. efrag)
+ *   Gamma^P_ia = sum_jb T_ij^ab B^P_jb                  (Appendix, Gamma, before
+ *                                                         its J^{-1/2} contraction)
+ *   P_ij = -sum_kab T_ik^ab X_jk^ab                      (Appendix, D^MP2_ij)
+ *   P_ab =  sum_ijc T_ij^ac X_ij^bc                      (Appendix, D^MP2_ab)
+ *
+ * All arithmetic is IEEE FP64.  Results are deterministic: the same inputs on
+ * the same GPU give bitwise identical outputs (no floating-point atomics).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device pointers; the caller owns every
+ *    buffer.  The library allocates no device memory: scratch space comes in
+ *    through the caller's workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it and the call returns without synchronising.
+ *  - Return value: RIMP2_OK, or a negative rimp2_status for an argument error
+ *    detected on the host (nothing is enqueued then).  rimp2_last_error()
+ *    returns a message for the calling thread's last non-OK return.
+ *  - Conditions only the device can see (an orbital-energy gap that would make
+ *    a denominator >= 0, or a NaN orbital energy) are written as RIMP2_EGAP to
+ *    the device status word in the workspace; every kernel of the call then
+ *    does nothing and the outputs are left unwritten.  Read it with
+ *    rimp2_read_status() after the stream has run the call.
+ *  - Layouts are row-major with the last index fastest:
+ *      B, Gamma  [nocc][nvir][naux]     eps_occ [nocc]    eps_vir [nvir]
+ *      P_ij, e_pair [nocc][nocc]        P_ab [nvir][nvir] E [2] = (hi, lo)
+ *  - Sizes: 1 <= nocc, nvir, naux and nocc*nvir*naux < 2^62.
+ */
+#ifndef RIMP2_H
+#define RIMP2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RIMP2_OK = 0,
+  RIMP2_EINVAL = -1,     /* bad size, null required pointer, bad option */
+  RIMP2_ENOMEM = -2,     /* workspace smaller than rimp2_workspace_size() */
+  RIMP2_EWORKSPACE = -3, /* workspace pointer misaligned (needs 256 B) */
+  RIMP2_EDEVICE = -4,    /* a HIP runtime call failed (message says which) */
+  RIMP2_EGAP = -5,       /* device: max eps_occ >= min eps_vir, or NaN eps */
+  RIMP2_ENOTSUP = -6     /* option combination not supported */
+} rimp2_status;
+
+/* Arithmetic of the two large contractions, (ia|jb) and Gamma. */
+typedef enum {
+  RIMP2_FP64 = 0,       /* FP64 MFMA throughout */
+  RIMP2_SPLIT_BF16 = 1  /* (ia|jb) and Gamma as sums of exact BF16 slice
+                           products with FP32 accumulation over short K
+                           chunks and FP64 chunk sums (Ozaki splitting);
+                           denominators, amplitudes and E stay FP64 */
+} rimp2_precision;
+
+typedef struct {
+  int32_t precision;        /* rimp2_precision */
+  int32_t split_slices;     /* RIMP2_SPLIT_BF16: slices per operand, 2..8 (0 = 6) */
+  int32_t slab_group;       /* occupied orbitals per slab group, 0 = largest that
+                               fits slab_budget_bytes (see rimp2_workspace_size) */
+  int32_t reserved0;
+  size_t  slab_budget_bytes;/* cap on the slab part of the workspace when
+                               slab_group == 0; 0 = 64 GiB */
+  const uint8_t* pair_skip; /* device [nocc][nocc] or NULL: nonzero (i,j) marks
+                               an occupied pair whose (ia|jb) block is skipped
+                               (screening); must be symmetric */
+} rimp2_opts;
+
+/* Library version, major*10000 + minor*100 + patch. */
+int rimp2_version(void);
+
+/* Message for the calling thread's last non-OK return (never NULL). */
+const char* rimp2_last_error(void);
+
+/* Name of a rimp2_status value. */
+const char* rimp2_status_string(int status);
+
+/*
+ * Bytes of device workspace rimp2_fragment needs for these sizes, outputs and
+ * options.  `want` is a bit set of RIMP2_WANT_* naming the outputs the call
+ * will request; the workspace for a call must be at least this large for the
+ * same `want` and options.  `opts` may be NULL (defaults).
+ */
+enum { RIMP2_WANT_GAMMA = 1, RIMP2_WANT_DENSITY = 2 };
+int rimp2_workspace_size(int32_t nocc, int32_t nvir, int32_t naux, int32_t want,
+                         const rimp2_opts* opts, size_t* bytes);
+
+/*
+ * One fragment.
+ *   B        device, read  [nocc][nvir][naux]   three-index factor B^P_ia
+ *   eps_occ  device, read  [nocc]               occupied orbital energies
+ *   eps_vir  device, read  [nvir]               virtual orbital energies
+ *   E        device, write [2]                  E_MP2 as hi + lo, where hi is
+ *            the sum rounded to FP64 and lo the rounded remainder (compensated,
+ *            fixed-order summation of the e_ij)
+ *   Gamma    device, write [nocc][nvir][naux] or NULL (not computed)
+ *   P_ij     device, write [nocc][nocc] or NULL (P_ij and P_ab are computed
+ *   P_ab     device, write [nvir][nvir] or NULL  together: both or neither)
+ *   e_pair   device, write [nocc][nocc] or NULL: e_ij for every ordered pair
+ *   workspace, workspace_bytes: device scratch, 256-byte aligned, at least
+ *            rimp2_workspace_size() bytes; its content on entry is ignored
+ * With opts->pair_skip set, e_ij of a skipped pair is 0 and the pair adds
+ * nothing to E, Gamma or P.
+ */
+int rimp2_fragment(int32_t nocc, int32_t nvir, int32_t naux,
+                   const double* B, const double* eps_occ, const double* eps_vir,
+                   double* E, double* Gamma, double* P_ij, double* P_ab, double* e_pair,
+                   void* workspace, size_t workspace_bytes,
+                   const rimp2_opts* opts, void* stream);
+
+/*
+ * Read the device status word of the last call that used this workspace
+ * (synchronises `stream` first).  Writes RIMP2_OK or RIMP2_EGAP to *status.
+ */
+int rimp2_read_status(const void* workspace, void* stream, int32_t* status);
+
+/* One fragment of a batch.  Pointers are device pointers as in rimp2_fragment;
+   Gamma, P_ij, P_ab and e_pair may be NULL. */
+typedef struct {
+  int32_t nocc, nvir, naux, reserved;
+  const double* B;
+  const double* eps_occ;
+  const double* eps_vir;
+  double* E;
+  double* Gamma;
+  double* P_ij;
+  double* P_ab;
+  double* e_pair;
+} rimp2_frag_desc;
+
+/*
+ * Many independent fragments (the monomers, dimers and trimers of an MBE3
+ * step).  `descs` is a HOST array of nfrag descriptors.  Fragments are run
+ * largest first.  status_dev (device, [nfrag] int32, may be NULL) receives
+ * each fragment's device status (RIMP2_OK or RIMP2_EGAP).  The workspace must
+ * be at least rimp2_batch_workspace_size() bytes for the same descriptors.
+ */
+int rimp2_batch_workspace_size(int32_t nfrag, const rimp2_frag_desc* descs,
+                               const rimp2_opts* opts, size_t* bytes);
+int rimp2_fragment_batch(int32_t nfrag, const rimp2_frag_desc* descs, int32_t* status_dev,
+                         void* workspace, size_t workspace_bytes,
+                         const rimp2_opts* opts, void* stream);
+
+/*
+ * Kernel timing (tracing).  While enabled, every kernel launch of the library
+ * is bracketed by a pair of HIP events recorded on the launch's own stream,
+ * and tagged with its role and its algorithmic FLOP and byte counts (FLOPs:
+ * 2 per multiply-add, (ia|jb) counted over unordered occupied pairs; bytes:
+ * compulsory HBM reads and writes of its operands).  rimp2_timing_collect
+ * waits for the recorded events, returns one entry per role with the summed
+ * event durations, and clears the records.  Timing adds a few microseconds
+ * per launch.
+ */
+typedef struct {
+  char    name[32];     /* kernel role, e.g. "ints_gemm", "gamma_gemm" */
+  int64_t launches;
+  double  total_ms;     /* sum of event durations over those launches */
+  double  alg_flops;    /* algorithmic FLOPs of those launches */
+  double  exec_flops;   /* multiply-add FLOPs the kernels execute */
+  double  alg_bytes;    /* algorithmic HBM bytes of those launches */
+} rimp2_kernel_stat;
+
+/* enable != 0 starts recording (and discards earlier records); 0 stops. */
+int rimp2_timing_enable(int enable);
+/* Writes up to `capacity` entries to `stats` and their number to *count. */
+int rimp2_timing_collect(rimp2_kernel_stat* stats, int32_t capacity, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIMP2_H */

@@ -88,7 +88,7 @@ def exact_sum(values) -> tuple[float, float]:
     return hi, lo
 
 
-def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True) -> dict:
+def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True, slabs=None) -> dict:
     """All outputs of the fragment kernel.
 
     Returns a dict with
@@ -98,6 +98,9 @@ def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True) -> d
       Gamma [nocc][nvir][naux], P_ij [nocc][nocc], P_ab [nvir][nvir]
     The loop runs over the occupied index k of the first orbital of each pair;
     for each k it forms V_kj, X_kj, T_kj for all j as plain matrices.
+    ``slabs`` (an iterable of k) restricts the loop to those k: then e_pair
+    rows and Gamma rows k are complete, the other rows stay zero, P_ij and P_ab
+    hold only those slabs' contributions and E sums the computed rows.
     """
     B = np.asarray(B)
     nocc, nvir, naux = B.shape
@@ -106,7 +109,7 @@ def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True) -> d
     Gamma = np.zeros((nocc, nvir, naux), dtype=dt) if gamma else None
     P_ij = np.zeros((nocc, nocc), dtype=dt) if density else None
     P_ab = np.zeros((nvir, nvir), dtype=dt) if density else None
-    for k in range(nocc):
+    for k in (range(nocc) if slabs is None else slabs):
         X_k = np.empty((nocc, nvir, nvir), dtype=dt)
         T_k = np.empty((nocc, nvir, nvir), dtype=dt)
         for j in range(nocc):

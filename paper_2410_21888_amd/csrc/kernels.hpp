@@ -1,0 +1,206 @@
+// Memory-bound kernels of the RI-MP2 fragment path (gfx950): orbital-energy
+// gap check, the amplitude pass (denominators, amplitudes, T = 2X - X^T and
+// pair energies), ordered split-K reduction and the compensated energy sum.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rimp2 {
+
+// Error-free transformations (Knuth's TwoSum, Dekker's FastTwoSum).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  e = b - (s - a);
+}
+// (ah, al) += (bh, bl), double-double addition with both error terms kept.
+__device__ __forceinline__ void dd_add(double& ah, double& al, double bh, double bl) {
+  double s, e, t, f;
+  two_sum(ah, bh, s, e);
+  two_sum(al, bl, t, f);
+  e += t;
+  fast_two_sum(s, e, s, e);
+  e += f;
+  fast_two_sum(s, e, ah, al);
+}
+
+// Fixed-order double-double reduction over the 256 threads of a workgroup.
+__device__ __forceinline__ void block_dd_reduce(double& hi, double& lo) {
+  __shared__ double sh[256], sl[256];
+  const int t = threadIdx.x;
+  sh[t] = hi;
+  sl[t] = lo;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      double h = sh[t], l = sl[t];
+      dd_add(h, l, sh[t + w], sl[t + w]);
+      sh[t] = h;
+      sl[t] = l;
+    }
+    __syncthreads();
+  }
+  hi = sh[0];
+  lo = sl[0];
+  __syncthreads();
+}
+
+// status = RIMP2_EGAP (-5) unless every denominator
+// ((eps_i + eps_j) - eps_a) - eps_b is negative.  FP addition is monotone, so
+// it is enough that the largest one, built from max eps_occ and min eps_vir
+// in the same order, is negative.  A NaN anywhere also fails.  One workgroup.
+__global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int nocc, const double* ev, int nvir,
+                                                        int32_t* status) {
+  __shared__ double smax[256], smin[256];
+  __shared__ int snan[256];
+  const int t = threadIdx.x;
+  double mx = -__builtin_inf(), mn = __builtin_inf();
+  int bad = 0;
+  for (int i = t; i < nocc; i += 256) { const double v = eo[i]; bad |= (v != v); mx = fmax(mx, v); }
+  for (int a = t; a < nvir; a += 256) { const double v = ev[a]; bad |= (v != v); mn = fmin(mn, v); }
+  smax[t] = mx; smin[t] = mn; snan[t] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      smax[t] = fmax(smax[t], smax[t + w]);
+      smin[t] = fmin(smin[t], smin[t + w]);
+      snan[t] |= snan[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double d = ((smax[0] + smax[0]) - smin[0]) - smin[0];
+    status[0] = (snan[0] || !(d < 0.0)) ? -5 : 0;
+  }
+}
+
+// Amplitude pass over one slab group.
+// V/X slab: element (kk, a, j, b) at S[((kk*nvir + a)*nocc + j)*nvir + b], kk < g.
+// One workgroup per occupied pair (k = k0 + kk, j).  For each pair of 32x32
+// tiles (ta <= tb) of the nvir x nvir block it reads V at (a,b) and (b,a),
+// forms X = V / D with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b in that
+// order (so X^T uses D[b,a] rounded its own way), then T = 2X - X^T, writes
+// X over V and T to the T slab (unless energy_only), and accumulates
+// e_kj = sum_ab T[a,b] V[a,b] with compensated per-thread sums and a fixed
+// reduction order.  pair_skip (may be null) zeroes skipped pairs.
+constexpr int AT = 32;
+__global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
+                                                        int nocc, int nvir, int k0, int energy_only,
+                                                        const uint8_t* pair_skip, double* e_pair,
+                                                        const int32_t* status) {
+  if (*status != 0) return;
+  __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];
+  const int kk = blockIdx.x / nocc, j = blockIdx.x - kk * nocc, k = k0 + kk;
+  const int64_t ld = (int64_t)nocc * nvir;
+  double* blk = S + ((int64_t)kk * nvir * nocc + j) * nvir;  // element (a,b) at blk[a*ld + b]
+  double* tblk = Tslab + ((int64_t)kk * nvir * nocc + j) * nvir;
+  const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
+  const double ekj = eo[k] + eo[j];
+  const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;  // 8 rows x 32 cols per pass
+  const int nt = (nvir + AT - 1) / AT;
+  double sh = 0.0, sl = 0.0;
+  for (int ta = 0; ta < nt; ++ta) {
+    for (int tb = ta; tb < nt; ++tb) {
+      const bool diag = (ta == tb);
+      double vP[4], vQ[4], xP[4], xQ[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = tr0 + 8 * s;
+        const int a = ta * AT + r, b = tb * AT + tc;   // tile P element (a, b)
+        const int a2 = tb * AT + r, b2 = ta * AT + tc; // tile Q element (a2, b2)
+        double v = 0.0, x = 0.0;
+        if (a < nvir && b < nvir) {
+          v = skip ? 0.0 : blk[(int64_t)a * ld + b];
+          const double d = (ekj - ev[a]) - ev[b];
+          x = v / d;
+        }
+        vP[s] = v; xP[s] = x; XP[r][tc] = x;
+        v = 0.0; x = 0.0;
+        if (!diag && a2 < nvir && b2 < nvir) {
+          v = skip ? 0.0 : blk[(int64_t)a2 * ld + b2];
+          const double d = (ekj - ev[a2]) - ev[b2];
+          x = v / d;
+        }
+        vQ[s] = v; xQ[s] = x; XQ[r][tc] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = tr0 + 8 * s;
+        const int a = ta * AT + r, b = tb * AT + tc;
+        const double xt = diag ? XP[tc][r] : XQ[tc][r];   // X[b, a]
+        const double tv = 2.0 * xP[s] - xt;
+        if (a < nvir && b < nvir) {
+          double p = tv * vP[s], e;
+          two_sum(sh, p, sh, e);
+          sl += e;
+          if (!energy_only) { blk[(int64_t)a * ld + b] = xP[s]; tblk[(int64_t)a * ld + b] = tv; }
+        }
+        if (!diag) {
+          const int a2 = tb * AT + r, b2 = ta * AT + tc;
+          const double xt2 = XP[tc][r];
+          const double tv2 = 2.0 * xQ[s] - xt2;
+          if (a2 < nvir && b2 < nvir) {
+            double p = tv2 * vQ[s], e;
+            two_sum(sh, p, sh, e);
+            sl += e;
+            if (!energy_only) { blk[(int64_t)a2 * ld + b2] = xQ[s]; tblk[(int64_t)a2 * ld + b2] = tv2; }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double h, l;
+  fast_two_sum(sh, sl, h, l);
+  block_dd_reduce(h, l);
+  if (t == 0) e_pair[(int64_t)k * nocc + j] = h + l;
+}
+
+// out[m*ldo + n] = (accumulate ? out : 0) + alpha * sum_{z < splits} W[z*zs + m*ldw + n],
+// summed in increasing z.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(double* out, int64_t ldo, const double* W, int64_t ldw,
+                                                            int64_t zs, int splits, int64_t M, int64_t N, double alpha,
+                                                            int accumulate, const int32_t* status) {
+  if (*status != 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t m = idx / N, n = idx - m * N;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += W[z * zs + m * ldw + n];
+  double* o = out + m * ldo + n;
+  *o = (accumulate ? *o : 0.0) + alpha * s;
+}
+
+// E = sum of count values, compensated, fixed order; writes (hi, lo).
+__global__ __launch_bounds__(256) void energy_sum_kernel(const double* e, int64_t count, double* E,
+                                                         const int32_t* status) {
+  if (*status != 0) return;
+  double sh = 0.0, sl = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) {
+    double s, err;
+    two_sum(sh, e[i], s, err);
+    sh = s;
+    sl += err;
+  }
+  double h, l;
+  fast_two_sum(sh, sl, h, l);
+  block_dd_reduce(h, l);
+  if (threadIdx.x == 0) {
+    double hi, lo;
+    fast_two_sum(h, l, hi, lo);
+    E[0] = hi;
+    E[1] = lo;
+  }
+}
+
+// status_out[idx] = *status (per-fragment status of a batch).
+__global__ void copy_status_kernel(const int32_t* status, int32_t* status_out, int idx) {
+  if (threadIdx.x == 0) status_out[idx] = *status;
+}
+
+}  // namespace rimp2

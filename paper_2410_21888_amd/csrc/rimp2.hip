@@ -1,0 +1,434 @@
+// Host side of the C ABI declared in include/rimp2.h: argument checks,
+// workspace planning and the launch sequence of the RI-MP2 fragment kernel.
+//
+// Path for one fragment (all on the caller's stream, no host synchronisation):
+//   gap check -> for each slab group of g occupied orbitals k0..k0+g-1:
+//     (ia|jb) slab GEMM  V[(k,a),(j,b)] = sum_P B[k,a,P] B[j,b,P]       (Eq. MP2_ints)
+//     amplitude pass     X = V/D, T = 2X - X^T, e_kj = sum T V           (Appendix, X)
+//     Gamma GEMM         Gamma[k,a,P] = sum_(j,b) T[k,a,j,b] B[j,b,P]    (Appendix, Gamma)
+//     P_ab GEMM          P_ab += sum_(k,j,c) T[k,a,j,c] X[k,b,j,c]       (Appendix, D_ab)
+//     P_ij GEMM          P_ij -= sum_(k,a,b) T[k,a,i,b] X[k,a,j,b]       (Appendix, D_ij)
+//   -> compensated E = sum e_ij.
+// Slab layout [kk][a][j][b]: the (ia|jb) and Gamma GEMMs see plain row-major
+// matrices; P_ab and P_ij read the same slabs with a two-level reduction index.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/rimp2.h"
+#include "gemm_f64.hpp"
+#include "kernels.hpp"
+
+using namespace rimp2;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(RIMP2_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- kernel timing -------------------------------------------------------
+enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_NROLES };
+const char* const kRoleName[R_NROLES] = {"gap_check", "ints_gemm",     "amplitude",  "gamma_gemm", "pab_gemm",
+                                         "pij_gemm",  "splitk_reduce", "energy_sum", "status_copy"};
+struct TraceRec {
+  int role;
+  hipEvent_t e0, e1;
+  double af, ef, ab;
+};
+struct Tracer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+Tracer& tracer() {
+  static Tracer t;
+  return t;
+}
+
+// Launches `launch` on stream st; while timing is on, brackets it with events.
+template <class F>
+int traced(int role, double af, double ef, double ab, hipStream_t st, F&& launch) {
+  Tracer& T = tracer();
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(T.mu);
+    on = T.on;
+    for (int i = 0; on && i < 2; ++i) {
+      if (!T.pool.empty()) {
+        ev[i] = T.pool.back();
+        T.pool.pop_back();
+      } else {
+        HIP_TRY(hipEventCreate(&ev[i]));
+      }
+    }
+  }
+  if (on) HIP_TRY(hipEventRecord(ev[0], st));
+  launch();
+  HIP_TRY(hipGetLastError());
+  if (on) {
+    HIP_TRY(hipEventRecord(ev[1], st));
+    std::lock_guard<std::mutex> lk(T.mu);
+    T.recs.push_back(TraceRec{role, ev[0], ev[1], af, ef, ab});
+  }
+  return RIMP2_OK;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kTile = 128;        // M/N tile of the large GEMMs
+constexpr int64_t kSmallTile = 64;    // tile of the P_ij GEMM
+constexpr int kBK = 16;
+constexpr int kTargetWG = 1024;       // workgroups to aim for when splitting K
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Plan {
+  int64_t nocc, nvir, naux;
+  bool gamma, density;
+  int64_t g;                 // occupied orbitals per slab group
+  int64_t s_ab, s_ij, s_gam; // split-K factors
+  size_t off_status, off_V, off_T, off_e, off_pab, off_pij, off_gam, total;
+};
+
+int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density, const rimp2_opts* o, Plan* p) {
+  if (nocc < 1 || nvir < 1 || naux < 1 || nocc > (1 << 20) || nvir > (1 << 24) || naux > (1 << 24))
+    return fail(RIMP2_EINVAL, "sizes must be >= 1 (nocc=%lld nvir=%lld naux=%lld)", (long long)nocc,
+                (long long)nvir, (long long)naux);
+  if ((double)nocc * nvir * naux >= 4.6e18)
+    return fail(RIMP2_EINVAL, "nocc*nvir*naux too large");
+  if (o && o->precision != RIMP2_FP64)
+    return fail(RIMP2_ENOTSUP, "precision %d not supported by this entry point", o->precision);
+  p->nocc = nocc; p->nvir = nvir; p->naux = naux; p->gamma = gamma; p->density = density;
+  const bool need_T = gamma || density;
+  const double slab_per_k = (need_T ? 2.0 : 1.0) * 8.0 * (double)nocc * nvir * nvir;
+  int64_t g;
+  if (o && o->slab_group > 0) {
+    g = std::min<int64_t>(o->slab_group, nocc);
+  } else {
+    const double budget = (o && o->slab_budget_bytes) ? (double)o->slab_budget_bytes : 64.0 * (1ull << 30);
+    g = (int64_t)(budget / slab_per_k);
+    g = std::max<int64_t>(1, std::min<int64_t>(g, nocc));
+  }
+  p->g = g;
+  // split-K factors: enough workgroups to fill 256 CUs at two per CU
+  auto splits = [](int64_t tiles, int64_t K) {
+    int64_t s = std::max<int64_t>(1, cdiv(kTargetWG, tiles));
+    return std::max<int64_t>(1, std::min<int64_t>(s, K / 512));
+  };
+  p->s_ab = density ? splits(cdiv(nvir, kTile) * cdiv(nvir, kTile), g * nocc * nvir) : 0;
+  p->s_ij = density ? splits(cdiv(nocc, kSmallTile) * cdiv(nocc, kSmallTile), g * nvir * nvir) : 0;
+  p->s_gam = gamma ? splits(cdiv(g * nvir, kTile) * cdiv(naux, kTile), nocc * nvir) : 0;
+  size_t off = 0;
+  p->off_status = off; off = align_up(off + 64);
+  p->off_V = off; off = align_up(off + (size_t)(8.0 * g * nocc * nvir * nvir));
+  p->off_T = off; if (need_T) off = align_up(off + (size_t)(8.0 * g * nocc * nvir * nvir));
+  p->off_e = off; off = align_up(off + 8 * (size_t)nocc * nocc);
+  p->off_pab = off; if (density) off = align_up(off + 8 * (size_t)p->s_ab * nvir * nvir);
+  p->off_pij = off; if (density) off = align_up(off + 8 * (size_t)p->s_ij * nocc * nocc);
+  p->off_gam = off; if (gamma && p->s_gam > 1) off = align_up(off + 8 * (size_t)p->s_gam * g * nvir * naux);
+  p->total = off;
+  return RIMP2_OK;
+}
+
+template <int BM, int BN, bool NC, int ROLE>
+int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
+  gp.tiles_m = (int32_t)cdiv(gp.M, BM);
+  gp.tiles_n = (int32_t)cdiv(gp.N, BN);
+  gp.group_m = 8;
+  if (gp.kchunk <= 0) gp.kchunk = gp.K;
+  gp.kchunk = cdiv(gp.kchunk, kBK) * kBK;
+  gp.splits = (int32_t)cdiv(gp.K, gp.kchunk);
+  const int64_t nwg = (int64_t)gp.tiles_m * gp.tiles_n * gp.splits;
+  if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "GEMM grid too large (%lld workgroups)", (long long)nwg);
+  const double ef = 2.0 * (double)gp.M * gp.N * gp.K;
+  return traced(role, af, ef, ab, st, [&] {
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
+  });
+}
+
+KOperand kop(const double* base, int64_t rs, int64_t kdiv, int64_t ks1) { return KOperand{base, rs, kdiv, ks1}; }
+
+// Enqueue the whole path for one fragment.  Pointers already validated.
+int run_fragment(const Plan& P, const double* B, const double* eo, const double* ev, double* E, double* Gam,
+                 double* Pij, double* Pab, double* e_user, char* ws, const uint8_t* skip, hipStream_t st) {
+  const int64_t nocc = P.nocc, nvir = P.nvir, naux = P.naux, L = nocc * nvir;
+  const double o = (double)nocc, v = (double)nvir, x = (double)naux;
+  int32_t* status = (int32_t*)(ws + P.off_status);
+  double* V = (double*)(ws + P.off_V);
+  double* T = (double*)(ws + P.off_T);
+  double* ep = e_user ? e_user : (double*)(ws + P.off_e);
+  int rc;
+  if ((rc = traced(R_GAP, 0, 0, 8.0 * (o + v), st, [&] {
+         hipLaunchKernelGGL(gap_check_kernel, dim3(1), dim3(256), 0, st, eo, (int)nocc, ev, (int)nvir, status);
+       })))
+    return rc;
+  const bool energy_only = !(P.gamma || P.density);
+  for (int64_t k0 = 0; k0 < nocc; k0 += P.g) {
+    const int64_t gc = std::min<int64_t>(P.g, nocc - k0);
+    const double g = (double)gc, slab = 8.0 * g * o * v * v;
+    // (ia|jb) slab: rows (kk, a) of B starting at k0, columns (j, b) over all of B
+    {
+      GemmParams gp{};
+      gp.M = gc * nvir; gp.N = L; gp.K = naux; gp.kchunk = naux;
+      gp.A = kop(B + k0 * nvir * naux, naux, INT64_MAX, 0);
+      gp.Bk = kop(B, naux, INT64_MAX, 0);
+      gp.C = V; gp.ldc = L; gp.split_stride = 0; gp.status = status;
+      // unordered-pair share of this slab's ordered pairs
+      const double af = 2.0 * g * v * o * v * x * (o + 1.0) / (2.0 * o);
+      if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS>(gp, st, R_INTS, af, 8.0 * (g + o) * v * x + slab)))
+        return rc;
+    }
+    if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
+           hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * nocc)), dim3(256), 0, st, V, T, eo, ev,
+                              (int)nocc, (int)nvir, (int)k0, energy_only ? 1 : 0, skip, ep, status);
+         })))
+      return rc;
+    if (P.gamma) {
+      GemmParams gp{};
+      gp.M = gc * nvir; gp.N = naux; gp.K = L;
+      gp.kchunk = cdiv(L, P.s_gam);
+      gp.A = kop(T, L, INT64_MAX, 0);
+      gp.Bn = NOperand{B, naux};
+      double* out = Gam + k0 * nvir * naux;
+      const double af = 2.0 * g * v * x * o * v, ab = slab + 8.0 * o * v * x + 8.0 * g * v * x;
+      if (P.s_gam > 1) {
+        double* W = (double*)(ws + P.off_gam);
+        gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux; gp.status = status;
+        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA>(gp, st, R_GAMMA, af, ab))) return rc;
+        const int64_t splits = cdiv(L, cdiv(cdiv(L, P.s_gam), kBK) * kBK);
+        const int64_t n = gc * nvir * naux;
+        if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
+               hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, out, naux, W,
+                                  naux, gc * nvir * naux, (int)splits, gc * nvir, naux, 1.0, 0, status);
+             })))
+          return rc;
+      } else {
+        gp.C = out; gp.ldc = naux; gp.split_stride = 0; gp.status = status;
+        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA>(gp, st, R_GAMMA, af, ab))) return rc;
+      }
+    }
+    if (P.density) {
+      const int accumulate = k0 > 0 ? 1 : 0;
+      {  // P_ab[a,b] += sum over (kk, j, c) of T[kk,a,j,c] X[kk,b,j,c]
+        GemmParams gp{};
+        const int64_t K = gc * L;
+        gp.M = nvir; gp.N = nvir; gp.K = K;
+        gp.kchunk = cdiv(K, P.s_ab);
+        gp.A = kop(T, L, L, nvir * L);
+        gp.Bk = kop(V, L, L, nvir * L);
+        double* W = (double*)(ws + P.off_pab);
+        gp.C = W; gp.ldc = nvir; gp.split_stride = nvir * nvir; gp.status = status;
+        const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ab), kBK) * kBK);
+        if ((rc = launch_gemm<kTile, kTile, false, ROLE_PAB>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
+                                                             2.0 * slab + 8.0 * splits * v * v)))
+          return rc;
+        if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * v * v, st, [&] {
+               hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nvir * nvir, 256)), dim3(256), 0, st, Pab,
+                                  nvir, W, nvir, nvir * nvir, (int)splits, nvir, nvir, 1.0, accumulate, status);
+             })))
+          return rc;
+      }
+      {  // P_ij[i,j] -= sum over (kk, a, b) of T[kk,a,i,b] X[kk,a,j,b]
+        GemmParams gp{};
+        const int64_t K = gc * nvir * nvir;
+        gp.M = nocc; gp.N = nocc; gp.K = K;
+        gp.kchunk = cdiv(K, P.s_ij);
+        gp.A = kop(T, nvir, nvir, L);
+        gp.Bk = kop(V, nvir, nvir, L);
+        double* W = (double*)(ws + P.off_pij);
+        gp.C = W; gp.ldc = nocc; gp.split_stride = nocc * nocc; gp.status = status;
+        const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ij), kBK) * kBK);
+        if ((rc = launch_gemm<kSmallTile, kSmallTile, false, ROLE_PIJ>(gp, st, R_PIJ, 2.0 * o * o * g * v * v,
+                                                                       2.0 * slab + 8.0 * splits * o * o)))
+          return rc;
+        if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * o * o, st, [&] {
+               hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nocc * nocc, 256)), dim3(256), 0, st, Pij,
+                                  nocc, W, nocc, nocc * nocc, (int)splits, nocc, nocc, -1.0, accumulate, status);
+             })))
+          return rc;
+      }
+    }
+  }
+  return traced(R_ESUM, 0, 0, 8.0 * o * o, st, [&] {
+    hipLaunchKernelGGL(energy_sum_kernel, dim3(1), dim3(256), 0, st, ep, nocc * nocc, E, status);
+  });
+}
+
+int want_of(const double* Gam, const double* Pij, const double* Pab, int* want) {
+  if ((Pij == nullptr) != (Pab == nullptr))
+    return fail(RIMP2_EINVAL, "P_ij and P_ab must both be given or both be NULL");
+  *want = (Gam ? RIMP2_WANT_GAMMA : 0) | (Pij ? RIMP2_WANT_DENSITY : 0);
+  return RIMP2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rimp2_version(void) { return 10000; }
+
+const char* rimp2_last_error(void) { return g_err; }
+
+const char* rimp2_status_string(int s) {
+  switch (s) {
+    case RIMP2_OK: return "RIMP2_OK";
+    case RIMP2_EINVAL: return "RIMP2_EINVAL";
+    case RIMP2_ENOMEM: return "RIMP2_ENOMEM";
+    case RIMP2_EWORKSPACE: return "RIMP2_EWORKSPACE";
+    case RIMP2_EDEVICE: return "RIMP2_EDEVICE";
+    case RIMP2_EGAP: return "RIMP2_EGAP";
+    case RIMP2_ENOTSUP: return "RIMP2_ENOTSUP";
+    default: return "unknown rimp2 status";
+  }
+}
+
+int rimp2_workspace_size(int32_t nocc, int32_t nvir, int32_t naux, int32_t want, const rimp2_opts* opts,
+                         size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  if (want & ~(RIMP2_WANT_GAMMA | RIMP2_WANT_DENSITY)) return fail(RIMP2_EINVAL, "bad want mask %d", want);
+  Plan P;
+  int rc = make_plan(nocc, nvir, naux, want & RIMP2_WANT_GAMMA, want & RIMP2_WANT_DENSITY, opts, &P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return RIMP2_OK;
+}
+
+int rimp2_fragment(int32_t nocc, int32_t nvir, int32_t naux, const double* B, const double* eps_occ,
+                   const double* eps_vir, double* E, double* Gamma, double* P_ij, double* P_ab, double* e_pair,
+                   void* workspace, size_t workspace_bytes, const rimp2_opts* opts, void* stream) {
+  if (!B || !eps_occ || !eps_vir || !E || !workspace)
+    return fail(RIMP2_EINVAL, "B, eps_occ, eps_vir, E and workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  int want, rc;
+  if ((rc = want_of(Gamma, P_ij, P_ab, &want))) return rc;
+  Plan P;
+  if ((rc = make_plan(nocc, nvir, naux, want & RIMP2_WANT_GAMMA, want & RIMP2_WANT_DENSITY, opts, &P))) return rc;
+  if (workspace_bytes < P.total)
+    return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, P.total);
+  return run_fragment(P, B, eps_occ, eps_vir, E, Gamma, P_ij, P_ab, e_pair, (char*)workspace,
+                      opts ? opts->pair_skip : nullptr, (hipStream_t)stream);
+}
+
+int rimp2_read_status(const void* workspace, void* stream, int32_t* status) {
+  if (!workspace || !status) return fail(RIMP2_EINVAL, "workspace and status must not be NULL");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(status, workspace, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return RIMP2_OK;
+}
+
+int rimp2_batch_workspace_size(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, size_t* bytes) {
+  if (nfrag < 0 || (nfrag > 0 && !d) || !bytes) return fail(RIMP2_EINVAL, "bad batch arguments");
+  size_t mx = kAlign;
+  for (int32_t f = 0; f < nfrag; ++f) {
+    int want, rc;
+    if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return rc;
+    Plan P;
+    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &P)))
+      return fail(rc, "fragment %d: %s", f, g_err);
+    mx = std::max(mx, P.total);
+  }
+  *bytes = mx;
+  return RIMP2_OK;
+}
+
+int rimp2_fragment_batch(int32_t nfrag, const rimp2_frag_desc* d, int32_t* status_dev, void* workspace,
+                         size_t workspace_bytes, const rimp2_opts* opts, void* stream) {
+  if (nfrag < 0 || (nfrag > 0 && !d) || !workspace) return fail(RIMP2_EINVAL, "bad batch arguments");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  std::vector<Plan> plans(nfrag);
+  std::vector<int32_t> order(nfrag);
+  for (int32_t f = 0; f < nfrag; ++f) {
+    if (!d[f].B || !d[f].eps_occ || !d[f].eps_vir || !d[f].E)
+      return fail(RIMP2_EINVAL, "fragment %d: B, eps_occ, eps_vir and E must not be NULL", f);
+    int want, rc;
+    if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return rc;
+    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &plans[f])))
+      return fail(rc, "fragment %d: %s", f, g_err);
+    if (plans[f].total > workspace_bytes)
+      return fail(RIMP2_ENOMEM, "fragment %d needs %zu workspace bytes, have %zu", f, plans[f].total, workspace_bytes);
+    order[f] = f;
+  }
+  // largest first (by FLOP count of the (ia|jb) and Gamma contractions)
+  auto cost = [&](int32_t f) { return (double)d[f].nocc * d[f].nocc * d[f].nvir * d[f].nvir * d[f].naux; };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  hipStream_t st = (hipStream_t)stream;
+  for (int32_t f : order) {
+    int rc = run_fragment(plans[f], d[f].B, d[f].eps_occ, d[f].eps_vir, d[f].E, d[f].Gamma, d[f].P_ij, d[f].P_ab,
+                          d[f].e_pair, (char*)workspace, nullptr, st);
+    if (rc) return fail(rc, "fragment %d: %s", f, g_err);
+    if (status_dev) {
+      rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
+        hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, st, (const int32_t*)workspace, status_dev, (int)f);
+      });
+      if (rc) return rc;
+    }
+  }
+  return RIMP2_OK;
+}
+
+int rimp2_timing_enable(int enable) {
+  Tracer& T = tracer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (auto& r : T.recs) {
+    T.pool.push_back(r.e0);
+    T.pool.push_back(r.e1);
+  }
+  T.recs.clear();
+  T.on = enable != 0;
+  return RIMP2_OK;
+}
+
+int rimp2_timing_collect(rimp2_kernel_stat* stats, int32_t capacity, int32_t* count) {
+  if (!count || (capacity > 0 && !stats)) return fail(RIMP2_EINVAL, "bad timing_collect arguments");
+  Tracer& T = tracer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  rimp2_kernel_stat acc[R_NROLES];
+  memset(acc, 0, sizeof acc);
+  for (int r = 0; r < R_NROLES; ++r) snprintf(acc[r].name, sizeof acc[r].name, "%s", kRoleName[r]);
+  for (auto& r : T.recs) {
+    HIP_TRY(hipEventSynchronize(r.e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
+    rimp2_kernel_stat& a = acc[r.role];
+    a.launches += 1;
+    a.total_ms += ms;
+    a.alg_flops += r.af;
+    a.exec_flops += r.ef;
+    a.alg_bytes += r.ab;
+    T.pool.push_back(r.e0);
+    T.pool.push_back(r.e1);
+  }
+  T.recs.clear();
+  int32_t n = 0;
+  for (int r = 0; r < R_NROLES; ++r)
+    if (acc[r].launches > 0) {
+      if (n < capacity) stats[n] = acc[r];
+      ++n;
+    }
+  *count = std::min(n, capacity);
+  return RIMP2_OK;
+}
+
+}  // extern "C"
