@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--slab-group", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stats", action="store_true", help="print per-kernel statistics to stderr")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB device-to-device (a plain copy of known size, for "
+                         "scaling profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -136,6 +139,13 @@ def main():
     t1 = time.perf_counter()
     stats = rm.timing_collect()
     rm.timing_enable(False)
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print("[bench] timed %d step(s) in %.3f s" % (args.steps, t1 - t0), file=sys.stderr, flush=True)
 
     fl = rm.flops(nocc, nvir, naux)

@@ -14,8 +14,15 @@
 // v_mfma_f64_16x16x4f64.  Lane layout of that instruction on gfx950
 // (measured): lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
 // register r of lane l holds D[4r + l/16][l%16].  Operand tiles are staged
-// k-major in LDS (double-buffered, one barrier per BK chunk); the next chunk's
-// global loads are issued before the current chunk's MFMAs.
+// k-major in LDS (double-buffered, one barrier per BK chunk).  Global loads
+// are 16 bytes (two consecutive reduction indices, or two consecutive columns
+// of an N-contiguous operand) when the operands allow it (VEC); interior
+// tiles take an unmasked path with loop-invariant row offsets.  The next
+// chunk's loads are issued before the current chunk's MFMAs and stored to LDS
+// halfway through them.
+//
+// Triangular launches (TRI): for a symmetric result only tiles with
+// tile_m <= tile_n are computed and each is also written transposed.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -62,84 +69,120 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 // ROLE only gives each contraction its own kernel symbol (profiler names).
 enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3 };
 
-template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE>
+template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
-  static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 4 == 0, "tile shape");
-  static_assert(256 % BK == 0 && BM % (256 / BK) == 0 && BN % (256 / BK) == 0, "loader shape");
+  static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 8 == 0, "tile shape");
   if (p.status != nullptr && *p.status != 0) return;
+  typedef double d2 __attribute__((ext_vector_type(2)));
 
-  constexpr int LDA = BM + 1, LDB = BN + 1;
+  constexpr int LDA = BM + 2, LDB = BN + 2;
   constexpr int WTM = BM / 2, WTN = BN / 2, MI = WTM / 16, NI = WTN / 16;
-  constexpr int RSTEP = 256 / BK;             // rows covered per pass (K-contiguous loader)
+  constexpr int KP = BK / 2;                   // k pairs per row (K-contiguous loader)
+  constexpr int RSTEP = 256 / KP;              // rows per pass
+  static_assert(BM % RSTEP == 0 && BN % RSTEP == 0, "K loader shape");
   constexpr int AN = BM / RSTEP, BKN = BN / RSTEP;
-  constexpr int NSTEP = 256 / BN;             // k rows per pass (N-contiguous loader)
-  constexpr int BNN = B_NCONTIG ? BK / (NSTEP > 0 ? NSTEP : 1) : 0;
-  static_assert(!B_NCONTIG || (256 % BN == 0 && BK % (256 / BN) == 0), "N loader shape");
+  constexpr int NP = BN / 2;                   // column pairs per k row (N-contiguous loader)
+  constexpr int NSTEP = 256 / NP;              // k rows per pass
+  constexpr int BNN = B_NCONTIG ? BK / NSTEP : 1;
+  static_assert(!B_NCONTIG || (256 % NP == 0 && BK % NSTEP == 0), "N loader shape");
   constexpr int BREG = B_NCONTIG ? BNN : BKN;
 
   __shared__ double As[2][BK * LDA];
-  __shared__ double Bs[2][BK * LDB];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BK * LDB];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
 
   // logical workgroup -> (split, tile); tiles grouped group_m m-tiles wide
   const int wl = xcd_remap(blockIdx.x, gridDim.x);
-  const int ntiles = p.tiles_m * p.tiles_n;
-  const int z = wl / ntiles;
-  const int t = wl - z * ntiles;
-  const int gsz = p.group_m * p.tiles_n;
-  const int grp = t / gsz;
-  const int first_m = grp * p.group_m;
-  const int gm = min(p.group_m, p.tiles_m - first_m);
-  const int tin = t - grp * gsz;
-  const int tm = first_m + tin % gm;
-  const int tn = tin / gm;
+  int tm, tn, z;
+  if (TRI) {
+    // upper-triangular tiles (tm <= tn) of a tiles_m x tiles_m grid, row by row
+    const int ntri = p.tiles_m * (p.tiles_m + 1) / 2;
+    z = wl / ntri;
+    int t = wl - z * ntri;
+    tm = 0;
+    while (t >= p.tiles_m - tm) { t -= p.tiles_m - tm; ++tm; }
+    tn = tm + t;
+  } else {
+    const int ntiles = p.tiles_m * p.tiles_n;
+    z = wl / ntiles;
+    const int t = wl - z * ntiles;
+    const int gsz = p.group_m * p.tiles_n;
+    const int grp = t / gsz;
+    const int first_m = grp * p.group_m;
+    const int gm = min(p.group_m, p.tiles_m - first_m);
+    const int tin = t - grp * gsz;
+    tm = first_m + tin % gm;
+    tn = tin / gm;
+  }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 
   const int64_t kbeg = (int64_t)z * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int nchunks = (int)((kend - kbeg + BK - 1) / BK);
 
-  // loader state: this thread's reduction column and its two-level offset
-  const int kk = tid % BK, r0 = tid / BK;
-  int64_t ka = kbeg + kk;
-  int64_t aq = ka / p.A.kdiv, ar = ka - aq * p.A.kdiv;
-  int64_t bq = 0, br = 0;
-  if (!B_NCONTIG) { bq = ka / p.Bk.kdiv; br = ka - bq * p.Bk.kdiv; }
-  const int nn = tid % BN, kn0 = tid / BN;  // N-contiguous loader
+  // K-contiguous loaders: thread -> rows r0 + s*RSTEP, reduction pair (kk, kk+1)
+  const int kk = 2 * (tid % KP), r0 = tid / KP;
+  int64_t aq, ar, bq = 0, br = 0;
+  { const int64_t k = kbeg + kk; aq = k / p.A.kdiv; ar = k - aq * p.A.kdiv; }
+  if (!B_NCONTIG) { const int64_t k = kbeg + kk; bq = k / p.Bk.kdiv; br = k - bq * p.Bk.kdiv; }
+  // N-contiguous loader: thread -> column pair nn, k rows kn0 + s*NSTEP
+  const int nn = 2 * (tid % NP), kn0 = tid / NP;
+  const bool fullA = (m0 + BM <= p.M), fullB = (n0 + BN <= p.N);
 
-  double ra[AN], rb[BREG];
+  d2 ra[AN], rb[BREG];
 
+  // One K-contiguous operand tile: element (row, k) = base[row*rs + (k/kdiv)*ks1 + k%kdiv].
+  // (q, r) is this thread's position for k = kc + kk.  With VEC the host has
+  // checked that every pair (kk, kk+1) lies in one run and is 16-byte aligned.
+  // The masked path steps (q, r) to kk+1 without division.
+#define RIMP2_KLOAD(OP, ROW0, NROWS, FULLROWS, Q, R, DST, CNT)                                        \
+  {                                                                                                 \
+    if (VEC && (FULLROWS) && fullk) {                                                               \
+      const double* src = OP.base + ((ROW0) + r0) * OP.rs + (Q) * OP.ks1 + (R);                     \
+      const int64_t st = (int64_t)RSTEP * OP.rs;                                                    \
+      _Pragma("unroll") for (int s = 0; s < CNT; ++s) DST[s] = *(const d2*)(src + s * st);          \
+    } else {                                                                                        \
+      const int64_t k0 = kc + kk;                                                                   \
+      const int64_t off0 = (Q) * OP.ks1 + (R);                                                      \
+      const int64_t off1 = ((R) + 1 < OP.kdiv) ? off0 + 1 : ((Q) + 1) * OP.ks1;                     \
+      _Pragma("unroll") for (int s = 0; s < CNT; ++s) {                                             \
+        const int64_t row = (ROW0) + r0 + s * RSTEP;                                                \
+        const int64_t rb0 = min(row, (NROWS) - 1) * OP.rs;                                          \
+        const bool rv = row < (NROWS);                                                              \
+        const double v0 = (rv && k0 < kend) ? OP.base[rb0 + off0] : 0.0;                            \
+        const double v1 = (rv && k0 + 1 < kend) ? OP.base[rb0 + off1] : 0.0;                        \
+        DST[s][0] = v0;                                                                             \
+        DST[s][1] = v1;                                                                             \
+      }                                                                                             \
+    }                                                                                               \
+  }
   auto load_chunk = [&](int c) {
     const int64_t kc = kbeg + (int64_t)c * BK;
-    {
-      const bool kv = (kc + kk) < kend;
-      const int64_t coff = aq * p.A.ks1 + ar;
-#pragma unroll
-      for (int s = 0; s < AN; ++s) {
-        const int64_t r = m0 + r0 + s * RSTEP;
-        ra[s] = (kv && r < p.M) ? p.A.base[r * p.A.rs + coff] : 0.0;
-      }
-    }
+    const bool fullk = (kc + BK <= kend);
+    RIMP2_KLOAD(p.A, m0, p.M, fullA, aq, ar, ra, AN)
     if (!B_NCONTIG) {
-      const bool kv = (kc + kk) < kend;
-      const int64_t coff = bq * p.Bk.ks1 + br;
-#pragma unroll
-      for (int s = 0; s < BKN; ++s) {
-        const int64_t r = n0 + r0 + s * RSTEP;
-        rb[s] = (kv && r < p.N) ? p.Bk.base[r * p.Bk.rs + coff] : 0.0;
-      }
+      RIMP2_KLOAD(p.Bk, n0, p.N, fullB, bq, br, rb, BKN)
     } else {
       const int64_t n = n0 + nn;
+      if (VEC && fullB && fullk) {
+        const double* src = p.Bn.base + (kc + kn0) * p.Bn.ld + n;
+        const int64_t st = (int64_t)NSTEP * p.Bn.ld;
 #pragma unroll
-      for (int s = 0; s < BNN; ++s) {
-        const int64_t k = kc + kn0 + s * NSTEP;
-        rb[s] = (k < kend && n < p.N) ? p.Bn.base[k * p.Bn.ld + n] : 0.0;
+        for (int s = 0; s < BNN; ++s) rb[s] = *(const d2*)(src + s * st);
+      } else {
+#pragma unroll
+        for (int s = 0; s < BNN; ++s) {
+          const int64_t k = kc + kn0 + s * NSTEP;
+          const double* row = p.Bn.base + min(k, kend - 1) * p.Bn.ld;
+          const double x0 = (k < kend && n < p.N) ? row[n] : 0.0;
+          const double x1 = (k < kend && n + 1 < p.N) ? row[n + 1] : 0.0;
+          rb[s][0] = x0;
+          rb[s][1] = x1;
+        }
       }
     }
-  };
-  auto advance = [&]() {
     ar += BK;
     while (ar >= p.A.kdiv) { ar -= p.A.kdiv; ++aq; }
     if (!B_NCONTIG) {
@@ -147,15 +190,22 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
       while (br >= p.Bk.kdiv) { br -= p.Bk.kdiv; ++bq; }
     }
   };
+#undef RIMP2_KLOAD
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int s = 0; s < AN; ++s) As[buf][kk * LDA + r0 + s * RSTEP] = ra[s];
+    for (int s = 0; s < AN; ++s) {
+      As[buf][kk * LDA + r0 + s * RSTEP] = ra[s][0];
+      As[buf][(kk + 1) * LDA + r0 + s * RSTEP] = ra[s][1];
+    }
     if (!B_NCONTIG) {
 #pragma unroll
-      for (int s = 0; s < BKN; ++s) Bs[buf][kk * LDB + r0 + s * RSTEP] = rb[s];
+      for (int s = 0; s < BKN; ++s) {
+        Bs[buf][kk * LDB + r0 + s * RSTEP] = rb[s][0];
+        Bs[buf][(kk + 1) * LDB + r0 + s * RSTEP] = rb[s][1];
+      }
     } else {
 #pragma unroll
-      for (int s = 0; s < BNN; ++s) Bs[buf][(kn0 + s * NSTEP) * LDB + nn] = rb[s];
+      for (int s = 0; s < BNN; ++s) *(d2*)&Bs[buf][(kn0 + s * NSTEP) * LDB + nn] = rb[s];
     }
   };
 
@@ -167,16 +217,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
 
   if (nchunks > 0) {
     load_chunk(0);
-    advance();
     store_chunk(0);
     __syncthreads();
     for (int c = 0; c < nchunks; ++c) {
       const int buf = c & 1;
-      if (c + 1 < nchunks) { load_chunk(c + 1); advance(); }
+      const bool more = c + 1 < nchunks;
+      if (more) load_chunk(c + 1);
       const double* as = As[buf];
       const double* bs = Bs[buf];
 #pragma unroll
       for (int k4 = 0; k4 < BK; k4 += 4) {
+        if (k4 == BK / 2 && more) store_chunk(buf ^ 1);
         const int kr = k4 + (lane >> 4);
         double a[MI], b[NI];
 #pragma unroll
@@ -189,7 +240,6 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
           for (int j = 0; j < NI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
-      if (c + 1 < nchunks) store_chunk(buf ^ 1);
       __syncthreads();
     }
   }
@@ -203,7 +253,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm * WTM + i * 16 + 4 * r + (lane >> 4);
         const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (m < p.M && n < p.N) C[m * p.ldc + n] = acc[i][j][r];
+        if (m < p.M && n < p.N) {
+          C[m * p.ldc + n] = acc[i][j][r];
+          if (TRI && tm != tn) C[n * p.ldc + m] = acc[i][j][r];
+        }
       }
 }
 

@@ -99,10 +99,34 @@ constexpr size_t kAlign = 256;
 constexpr int64_t kTile = 128;        // M/N tile of the large GEMMs
 constexpr int64_t kSmallTile = 64;    // tile of the P_ij GEMM
 constexpr int kBK = 16;
-constexpr int kTargetWG = 1024;       // workgroups to aim for when splitting K
+constexpr int64_t kSlots = 512;       // resident GEMM workgroups: 2 per CU on 256 CUs
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Split-K factor for a launch of `tiles` output tiles over reduction length K:
+// the factor (at most 64, each split at least 2048 long) whose workgroup count
+// best fills whole waves of kSlots workgroups.
+int64_t choose_splits(int64_t tiles, int64_t K) {
+  if (tiles >= 8 * kSlots) return 1;
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, K / 2048));
+  int64_t best = 1;
+  double best_eff = -1.0;
+  for (int64_t s = 1; s <= smax; ++s) {
+    const int64_t total = tiles * s;
+    const double waves = (double)cdiv(total, kSlots);
+    // fill of the last wave, plus a small preference for more waves (tail effects)
+    const double eff = (double)total / (waves * kSlots) + 0.002 * std::min(waves, 8.0);
+    if (eff > best_eff + 1e-9) { best_eff = eff; best = s; }
+  }
+  return best;
+}
+
+// P_ab tile: 96 when it pads nvir by at least 8% less area than 128.
+bool pab_tile96(int64_t nvir) {
+  const double a128 = (double)cdiv(nvir, 128) * 128.0, a96 = (double)cdiv(nvir, 96) * 96.0;
+  return a96 * a96 < 0.92 * a128 * a128;
+}
 
 struct Plan {
   int64_t nocc, nvir, naux;
@@ -132,14 +156,11 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
     g = std::max<int64_t>(1, std::min<int64_t>(g, nocc));
   }
   p->g = g;
-  // split-K factors: enough workgroups to fill 256 CUs at two per CU
-  auto splits = [](int64_t tiles, int64_t K) {
-    int64_t s = std::max<int64_t>(1, cdiv(kTargetWG, tiles));
-    return std::max<int64_t>(1, std::min<int64_t>(s, K / 512));
-  };
-  p->s_ab = density ? splits(cdiv(nvir, kTile) * cdiv(nvir, kTile), g * nocc * nvir) : 0;
-  p->s_ij = density ? splits(cdiv(nocc, kSmallTile) * cdiv(nocc, kSmallTile), g * nvir * nvir) : 0;
-  p->s_gam = gamma ? splits(cdiv(g * nvir, kTile) * cdiv(naux, kTile), nocc * nvir) : 0;
+  // split-K factors (see choose_splits); P_ij uses upper-triangular tiles
+  const int64_t tab = pab_tile96(nvir) ? 96 : kTile, tij = cdiv(nocc, kSmallTile);
+  p->s_ab = density ? choose_splits(cdiv(nvir, tab) * cdiv(nvir, tab), g * nocc * nvir) : 0;
+  p->s_ij = density ? choose_splits(tij * (tij + 1) / 2, g * nvir * nvir) : 0;
+  p->s_gam = gamma ? choose_splits(cdiv(g * nvir, kTile) * cdiv(naux, kTile), nocc * nvir) : 0;
   size_t off = 0;
   p->off_status = off; off = align_up(off + 64);
   p->off_V = off; off = align_up(off + (size_t)(8.0 * g * nocc * nvir * nvir));
@@ -152,7 +173,14 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   return RIMP2_OK;
 }
 
-template <int BM, int BN, bool NC, int ROLE>
+// 16-byte loads need 16-byte aligned bases and even strides (so every pair of
+// reduction indices, and every pair of N-contiguous columns, is aligned).
+bool kop_vec(const KOperand& o, int64_t K) {
+  const bool plain = o.kdiv >= K;
+  return (uintptr_t)o.base % 16 == 0 && o.rs % 2 == 0 && (plain || (o.kdiv % 2 == 0 && o.ks1 % 2 == 0));
+}
+
+template <int BM, int BN, bool NC, int ROLE, bool TRI>
 int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   gp.tiles_m = (int32_t)cdiv(gp.M, BM);
   gp.tiles_n = (int32_t)cdiv(gp.N, BN);
@@ -160,13 +188,21 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   if (gp.kchunk <= 0) gp.kchunk = gp.K;
   gp.kchunk = cdiv(gp.kchunk, kBK) * kBK;
   gp.splits = (int32_t)cdiv(gp.K, gp.kchunk);
-  const int64_t nwg = (int64_t)gp.tiles_m * gp.tiles_n * gp.splits;
+  if (TRI && (gp.M != gp.N || BM != BN)) return fail(RIMP2_EINVAL, "triangular GEMM needs a square tile grid");
+  const int64_t tiles = TRI ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
+  const int64_t nwg = tiles * gp.splits;
   if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "GEMM grid too large (%lld workgroups)", (long long)nwg);
-  const double ef = 2.0 * (double)gp.M * gp.N * gp.K;
+  const bool vec = kop_vec(gp.A, gp.K) && gp.kchunk % 2 == 0 &&
+                   (NC ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
+  const double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
   return traced(role, af, ef, ab, st, [&] {
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
+    if (vec)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
+    else
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, false, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
   });
 }
+
 
 KOperand kop(const double* base, int64_t rs, int64_t kdiv, int64_t ks1) { return KOperand{base, rs, kdiv, ks1}; }
 
@@ -197,7 +233,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       gp.C = V; gp.ldc = L; gp.split_stride = 0; gp.status = status;
       // unordered-pair share of this slab's ordered pairs
       const double af = 2.0 * g * v * o * v * x * (o + 1.0) / (2.0 * o);
-      if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS>(gp, st, R_INTS, af, 8.0 * (g + o) * v * x + slab)))
+      if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS, false>(gp, st, R_INTS, af, 8.0 * (g + o) * v * x + slab)))
         return rc;
     }
     if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
@@ -216,7 +252,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       if (P.s_gam > 1) {
         double* W = (double*)(ws + P.off_gam);
         gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux; gp.status = status;
-        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA>(gp, st, R_GAMMA, af, ab))) return rc;
+        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA, false>(gp, st, R_GAMMA, af, ab))) return rc;
         const int64_t splits = cdiv(L, cdiv(cdiv(L, P.s_gam), kBK) * kBK);
         const int64_t n = gc * nvir * naux;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
@@ -226,7 +262,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
           return rc;
       } else {
         gp.C = out; gp.ldc = naux; gp.split_stride = 0; gp.status = status;
-        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA>(gp, st, R_GAMMA, af, ab))) return rc;
+        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA, false>(gp, st, R_GAMMA, af, ab))) return rc;
       }
     }
     if (P.density) {
@@ -241,9 +277,12 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         double* W = (double*)(ws + P.off_pab);
         gp.C = W; gp.ldc = nvir; gp.split_stride = nvir * nvir; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ab), kBK) * kBK);
-        if ((rc = launch_gemm<kTile, kTile, false, ROLE_PAB>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
-                                                             2.0 * slab + 8.0 * splits * v * v)))
-          return rc;
+        rc = pab_tile96(nvir)
+                 ? launch_gemm<96, 96, false, ROLE_PAB, false>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
+                                                              2.0 * slab + 8.0 * splits * v * v)
+                 : launch_gemm<kTile, kTile, false, ROLE_PAB, false>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
+                                                                    2.0 * slab + 8.0 * splits * v * v);
+        if (rc) return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * v * v, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nvir * nvir, 256)), dim3(256), 0, st, Pab,
                                   nvir, W, nvir, nvir * nvir, (int)splits, nvir, nvir, 1.0, accumulate, status);
@@ -260,8 +299,9 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         double* W = (double*)(ws + P.off_pij);
         gp.C = W; gp.ldc = nocc; gp.split_stride = nocc * nocc; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ij), kBK) * kBK);
-        if ((rc = launch_gemm<kSmallTile, kSmallTile, false, ROLE_PIJ>(gp, st, R_PIJ, 2.0 * o * o * g * v * v,
-                                                                       2.0 * slab + 8.0 * splits * o * o)))
+        // each slab's contribution to P_ij is symmetric: upper-triangular tiles, mirrored
+        if ((rc = launch_gemm<kSmallTile, kSmallTile, false, ROLE_PIJ, true>(gp, st, R_PIJ, 2.0 * o * o * g * v * v,
+                                                                             2.0 * slab + 8.0 * splits * o * o)))
           return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * o * o, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nocc * nocc, 256)), dim3(256), 0, st, Pij,
