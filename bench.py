@@ -82,6 +82,12 @@ def main():
     ap.add_argument("--decay", type=float, default=1200.0)
     ap.add_argument("--seed", type=int, default=1001)
     ap.add_argument("--slab-group", type=int, default=0)
+    ap.add_argument("--precision", choices=["fp64", "split"], default="fp64",
+                    help="split: (ia|jb) and Gamma as INT8 digit products (Ozaki scheme)")
+    ap.add_argument("--split-slices", type=int, default=0, help="digits per operand of (ia|jb) (0 = 7)")
+    ap.add_argument("--split-slices-gamma", type=int, default=0, help="digits per operand of Gamma (0 = 5)")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="after the timed steps run one FP64 step and report the differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stats", action="store_true", help="print per-kernel statistics to stderr")
     ap.add_argument("--calib-copy", action="store_true",
@@ -116,7 +122,9 @@ def main():
     Pij = torch.empty((nocc, nocc), **f64)
     Pab = torch.empty((nvir, nvir), **f64)
     ep = torch.empty((nocc, nocc), **f64)
-    opts = rm.make_opts(slab_group=args.slab_group)
+    opts = rm.make_opts(slab_group=args.slab_group,
+                        precision=rm.SPLIT_INT8 if args.precision == "split" else rm.FP64,
+                        split_slices=args.split_slices, split_slices_gamma=args.split_slices_gamma)
     ws = torch.empty(rm.workspace_size(nocc, nvir, naux, True, True, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -189,6 +197,31 @@ def main():
                      "traffic": traffic},
         "E_hi": float(E[0]), "E_lo": float(E[1]),
     }
+    if args.precision == "split":
+        out["dtype"] = "int8 digit products (Ozaki), f64 elsewhere"
+        out["config"]["precision"] = "split-int8 ints=%d gamma=%d digits" % (args.split_slices or 7,
+                                                                             args.split_slices_gamma or 5)
+        out["roofline"]["note"] = "FP64-equivalent rate of the split kernel against the FP64 peak"
+    if args.compare_fp64:
+        import math
+        G_s, ep_s, Pij_s, Pab_s, E_s = G.clone(), ep.clone(), Pij.clone(), Pab.clone(), E.clone()
+        del ws
+        torch.cuda.empty_cache()
+        o64 = rm.make_opts(slab_group=args.slab_group)
+        ws64 = torch.empty(rm.workspace_size(nocc, nvir, naux, True, True, o64), dtype=torch.uint8, device=dev)
+        t2 = time.perf_counter()
+        rm.fragment_into(B, deo, dev_, E, G, Pij, Pab, ep, workspace=ws64, opts=o64)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        e64 = E.cpu().numpy()
+        es = E_s.cpu().numpy()
+        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        out["vs_fp64"] = {
+            "abs_dE_Eh": abs(math.fsum([float(es[0]), float(es[1]), -float(e64[0]), -float(e64[1])])),
+            "gamma_rel_fro": rel(G_s, G), "p_ij_rel_fro": rel(Pij_s, Pij), "p_ab_rel_fro": rel(Pab_s, Pab),
+            "e_pair_rel_fro": rel(ep_s, ep), "fp64_step_s": t3 - t2,
+            "speedup_vs_fp64": (t3 - t2) / dt,
+        }
     if not args.no_cpu_baseline:
         B_np = B_host.numpy()
         ref, cb = cpu_baseline(B_np, eo, ev, nocc, fl["algorithmic"], [0])

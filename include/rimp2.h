@@ -59,18 +59,24 @@ typedef enum {
 /* Arithmetic of the two large contractions, (ia|jb) and Gamma. */
 typedef enum {
   RIMP2_FP64 = 0,       /* FP64 MFMA throughout */
-  RIMP2_SPLIT_BF16 = 1  /* (ia|jb) and Gamma as sums of exact BF16 slice
-                           products with FP32 accumulation over short K
-                           chunks and FP64 chunk sums (Ozaki splitting);
-                           denominators, amplitudes and E stay FP64 */
+  RIMP2_SPLIT_INT8 = 1  /* (ia|jb) and Gamma as split products (Ozaki scheme):
+                           each FP64 row is scaled by a power of two and cut
+                           into S signed 7-bit digits; the S(S+1)/2 digit
+                           products that matter are summed exactly in INT32 on
+                           INT8 MFMA and combined in FP64.  Denominators,
+                           amplitudes, E, P_ij and P_ab stay FP64.  The error
+                           of a product is about 2^-7S relative to its
+                           operands' row maxima. */
 } rimp2_precision;
 
 typedef struct {
   int32_t precision;        /* rimp2_precision */
-  int32_t split_slices;     /* RIMP2_SPLIT_BF16: slices per operand, 2..8 (0 = 6) */
+  int32_t split_slices;     /* RIMP2_SPLIT_INT8: digits per operand of (ia|jb),
+                               3..7 (0 = 7) */
   int32_t slab_group;       /* occupied orbitals per slab group, 0 = largest that
                                fits slab_budget_bytes (see rimp2_workspace_size) */
-  int32_t reserved0;
+  int32_t split_slices_gamma; /* RIMP2_SPLIT_INT8: digits per operand of Gamma,
+                               3..7 (0 = 5) */
   size_t  slab_budget_bytes;/* cap on the slab part of the workspace when
                                slab_group == 0; 0 = 64 GiB */
   const uint8_t* pair_skip; /* device [nocc][nocc] or NULL: nonzero (i,j) marks

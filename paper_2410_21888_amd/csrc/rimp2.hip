@@ -24,6 +24,7 @@
 #include "../../include/rimp2.h"
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
+#include "split_int8.hpp"
 
 using namespace rimp2;
 
@@ -47,9 +48,11 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 // ---- kernel timing -------------------------------------------------------
-enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_NROLES };
-const char* const kRoleName[R_NROLES] = {"gap_check", "ints_gemm",     "amplitude",  "gamma_gemm", "pab_gemm",
-                                         "pij_gemm",  "splitk_reduce", "energy_sum", "status_copy"};
+enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
+            R_NROLES };
+const char* const kRoleName[R_NROLES] = {"gap_check",  "ints_gemm",     "amplitude",  "gamma_gemm",
+                                         "pab_gemm",   "pij_gemm",      "splitk_reduce", "energy_sum",
+                                         "status_copy", "digit_split", "ints_oz8",   "gamma_oz8"};
 struct TraceRec {
   int role;
   hipEvent_t e0, e1;
@@ -131,6 +134,10 @@ bool pab_tile96(int64_t nvir) {
 struct Plan {
   int64_t nocc, nvir, naux;
   bool gamma, density;
+  bool split;                // RIMP2_SPLIT_INT8
+  int sv, sg;                // digits per operand of (ia|jb) and of Gamma
+  int64_t kpv, kpg;          // padded reduction lengths of the split products
+  size_t off_dbv, off_ev, off_dbg, off_eg, off_cmax, off_dt, off_et;
   int64_t g;                 // occupied orbitals per slab group
   int64_t s_ab, s_ij, s_gam; // split-K factors
   size_t off_status, off_V, off_T, off_e, off_pab, off_pij, off_gam, total;
@@ -142,9 +149,16 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
                 (long long)nvir, (long long)naux);
   if ((double)nocc * nvir * naux >= 4.6e18)
     return fail(RIMP2_EINVAL, "nocc*nvir*naux too large");
-  if (o && o->precision != RIMP2_FP64)
-    return fail(RIMP2_ENOTSUP, "precision %d not supported by this entry point", o->precision);
+  if (o && o->precision != RIMP2_FP64 && o->precision != RIMP2_SPLIT_INT8)
+    return fail(RIMP2_ENOTSUP, "precision %d is not supported", o->precision);
   p->nocc = nocc; p->nvir = nvir; p->naux = naux; p->gamma = gamma; p->density = density;
+  p->split = o && o->precision == RIMP2_SPLIT_INT8;
+  p->sv = (o && o->split_slices) ? o->split_slices : 7;
+  p->sg = (o && o->split_slices_gamma) ? o->split_slices_gamma : 5;
+  if (p->split && (p->sv < 3 || p->sv > 7 || p->sg < 3 || p->sg > 7))
+    return fail(RIMP2_EINVAL, "split digit counts must be 3..7 (got %d and %d)", p->sv, p->sg);
+  p->kpv = cdiv(naux, 64) * 64;
+  p->kpg = cdiv(nocc * nvir, 64) * 64;
   const bool need_T = gamma || density;
   const double slab_per_k = (need_T ? 2.0 : 1.0) * 8.0 * (double)nocc * nvir * nvir;
   int64_t g;
@@ -168,7 +182,20 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->off_e = off; off = align_up(off + 8 * (size_t)nocc * nocc);
   p->off_pab = off; if (density) off = align_up(off + 8 * (size_t)p->s_ab * nvir * nvir);
   p->off_pij = off; if (density) off = align_up(off + 8 * (size_t)p->s_ij * nocc * nocc);
-  p->off_gam = off; if (gamma && p->s_gam > 1) off = align_up(off + 8 * (size_t)p->s_gam * g * nvir * naux);
+  p->off_gam = off; if (gamma && p->s_gam > 1 && !p->split) off = align_up(off + 8 * (size_t)p->s_gam * g * nvir * naux);
+  p->off_dbv = p->off_ev = p->off_dbg = p->off_eg = p->off_cmax = p->off_dt = p->off_et = off;
+  if (p->split) {
+    const int64_t L = nocc * nvir;
+    p->off_dbv = off; off = align_up(off + (size_t)p->sv * L * p->kpv);
+    p->off_ev = off; off = align_up(off + 4 * (size_t)L);
+    if (gamma) {
+      p->off_dbg = off; off = align_up(off + (size_t)p->sg * naux * p->kpg);
+      p->off_eg = off; off = align_up(off + 4 * (size_t)naux);
+      p->off_cmax = off; off = align_up(off + 8 * (size_t)naux);
+      p->off_dt = off; off = align_up(off + (size_t)p->sg * g * nvir * p->kpg);
+      p->off_et = off; off = align_up(off + 4 * (size_t)g * nvir);
+    }
+  }
   p->total = off;
   return RIMP2_OK;
 }
@@ -204,6 +231,53 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
 }
 
 
+template <int S>
+void launch_split_rows(const double* X, int64_t rows, int64_t K, int64_t ld, int8_t* D, int64_t kp, int32_t* e,
+                       const int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(split_rows_kernel<S>, dim3((unsigned)rows), dim3(256), 0, st, X, rows, K, ld, D, kp, e, status);
+}
+template <int S>
+void launch_split_cols(const double* X, int64_t K, int64_t N, int64_t ld, const unsigned long long* cmax, int8_t* D,
+                       int64_t kp, int32_t* e, const int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(split_cols_kernel<S>, dim3((unsigned)cdiv(kp, 32), (unsigned)cdiv(N, 32)), dim3(256), 0, st, X, K,
+                     N, ld, cmax, D, kp, e, status);
+}
+template <int S>
+void launch_oz8(OzParams op, hipStream_t st) {
+  const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
+  hipLaunchKernelGGL(gemm_oz8_kernel<S>, dim3((unsigned)nwg), dim3(256), 0, st, op);
+}
+#define RIMP2_SWITCH_S(S, CALL)                                   \
+  switch (S) {                                                    \
+    case 3: { constexpr int SS = 3; CALL; } break;                \
+    case 4: { constexpr int SS = 4; CALL; } break;                \
+    case 5: { constexpr int SS = 5; CALL; } break;                \
+    case 6: { constexpr int SS = 6; CALL; } break;                \
+    default: { constexpr int SS = 7; CALL; } break;               \
+  }
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// C[m, n] (m < M, n < N) from split digits; A rows start at a_row0.
+int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32_t* ea, const int8_t* B,
+            int64_t b_slice, const int32_t* eb, int64_t M, int64_t N, int64_t kp, double* C, int64_t ldc,
+            const int32_t* status, int role, double af, double ab, hipStream_t st) {
+  OzParams op{};
+  op.M = M; op.N = N; op.kp = kp;
+  op.A = A; op.a_slice = a_slice; op.a_row0 = a_row0;
+  op.B = B; op.b_slice = b_slice; op.ea = ea; op.eb = eb;
+  op.C = C; op.ldc = ldc;
+  op.tiles_m = (int32_t)cdiv(M, 64); op.tiles_n = (int32_t)cdiv(N, 64); op.group_m = 8;
+  op.status = status;
+  const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
+  if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "split GEMM grid too large");
+  const double ef = 2.0 * (double)M * N * kp;
+  return traced(role, af, ef, ab, st, [&] { RIMP2_SWITCH_S(S, launch_oz8<SS>(op, st)); });
+}
+
 KOperand kop(const double* base, int64_t rs, int64_t kdiv, int64_t ks1) { return KOperand{base, rs, kdiv, ks1}; }
 
 // Enqueue the whole path for one fragment.  Pointers already validated.
@@ -221,6 +295,36 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
        })))
     return rc;
   const bool energy_only = !(P.gamma || P.density);
+  int8_t* dbv = (int8_t*)(ws + P.off_dbv);
+  int32_t* exv = (int32_t*)(ws + P.off_ev);
+  int8_t* dbg = (int8_t*)(ws + P.off_dbg);
+  int32_t* exg = (int32_t*)(ws + P.off_eg);
+  int8_t* dt = (int8_t*)(ws + P.off_dt);
+  int32_t* ext = (int32_t*)(ws + P.off_et);
+  if (P.split) {
+    // digits of every B row (both operands of the (ia|jb) products)
+    if ((rc = traced(R_SPLIT, 0, 0, 8.0 * L * naux + (double)P.sv * L * P.kpv, st, [&] {
+           RIMP2_SWITCH_S(P.sv, launch_split_rows<SS>(B, L, naux, naux, dbv, P.kpv, exv, status, st));
+         })))
+      return rc;
+    if (P.gamma) {
+      // column-scaled, transposed digits of B as the [(j,b)][P] operand of Gamma
+      unsigned long long* cmax = (unsigned long long*)(ws + P.off_cmax);
+      if ((rc = traced(R_SPLIT, 0, 0, 8.0 * naux, st, [&] {
+             hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, cmax, naux);
+           })))
+        return rc;
+      if ((rc = traced(R_SPLIT, 0, 0, 8.0 * L * naux, st, [&] {
+             hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(naux, 256), (unsigned)cdiv(L, 1024)), dim3(256), 0,
+                                st, B, L, naux, naux, cmax, status);
+           })))
+        return rc;
+      if ((rc = traced(R_SPLIT, 0, 0, 8.0 * L * naux + (double)P.sg * naux * P.kpg, st, [&] {
+             RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(B, L, naux, naux, cmax, dbg, P.kpg, exg, status, st));
+           })))
+        return rc;
+    }
+  }
   for (int64_t k0 = 0; k0 < nocc; k0 += P.g) {
     const int64_t gc = std::min<int64_t>(P.g, nocc - k0);
     const double g = (double)gc, slab = 8.0 * g * o * v * v;
@@ -233,8 +337,14 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       gp.C = V; gp.ldc = L; gp.split_stride = 0; gp.status = status;
       // unordered-pair share of this slab's ordered pairs
       const double af = 2.0 * g * v * o * v * x * (o + 1.0) / (2.0 * o);
-      if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS, false>(gp, st, R_INTS, af, 8.0 * (g + o) * v * x + slab)))
+      if (P.split) {
+        if ((rc = run_oz8(P.sv, dbv, L * P.kpv, k0 * nvir, exv, dbv, L * P.kpv, exv, gc * nvir, L, P.kpv, V, L,
+                          status, R_INTS8, af, (double)P.sv * (g * v + o * v) * P.kpv + slab, st)))
+          return rc;
+      } else if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS, false>(gp, st, R_INTS, af,
+                                                                          8.0 * (g + o) * v * x + slab))) {
         return rc;
+      }
     }
     if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
            hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * nocc)), dim3(256), 0, st, V, T, eo, ev,
@@ -249,7 +359,15 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       gp.Bn = NOperand{B, naux};
       double* out = Gam + k0 * nvir * naux;
       const double af = 2.0 * g * v * x * o * v, ab = slab + 8.0 * o * v * x + 8.0 * g * v * x;
-      if (P.s_gam > 1) {
+      if (P.split) {
+        if ((rc = traced(R_SPLIT, 0, 0, slab + (double)P.sg * g * v * P.kpg, st, [&] {
+               RIMP2_SWITCH_S(P.sg, launch_split_rows<SS>(T, gc * nvir, L, L, dt, P.kpg, ext, status, st));
+             })))
+          return rc;
+        if ((rc = run_oz8(P.sg, dt, gc * nvir * P.kpg, 0, ext, dbg, naux * P.kpg, exg, gc * nvir, naux, P.kpg, out,
+                          naux, status, R_GAMMA8, af, (double)P.sg * (g * v + x) * P.kpg + 8.0 * g * v * x, st)))
+          return rc;
+      } else if (P.s_gam > 1) {
         double* W = (double*)(ws + P.off_gam);
         gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux; gp.status = status;
         if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA, false>(gp, st, R_GAMMA, af, ab))) return rc;

@@ -1,0 +1,249 @@
+// Split-precision (Ozaki-style) products on gfx950 INT8 MFMA.
+//
+// A row (or column) x of an FP64 operand is scaled by 2^-e with
+// e = ilogb(max |x|) + 1, so |x| 2^-e < 1, and written as S balanced base-128
+// digits:  x = 2^e / 64 * sum_{s=1..S} d_s 128^(1-s),  |d_s| <= 64,  extracted
+// exactly in FP64 with round-to-nearest (y = x 2^(6-e); d = rint(y);
+// y = (y - d) * 128; ...).  The dropped remainder is at most 2^-7S relative
+// to the row maximum.
+//
+// C = A B^T is then
+//   C[m,n] = 2^(ea[m] + eb[n] - 12) * sum_{L=2..S+1} 128^(2-L) * sum_{s+t=L} D_s(A) D_t(B)^T
+// (the products with s + t > S + 1 are below the digit truncation and are
+// dropped: S(S+1)/2 integer products).  Each level is summed exactly in INT32
+// by v_mfma_i32_16x16x64_i8; to rule out overflow the levels are moved into
+// FP64 accumulators every kFlushK reduction steps (S * kFlushK * 64 * 64 < 2^31).
+//
+// MFMA lane layout (measured on gfx950): lane l supplies A[l%16][16(l/16)+b]
+// and B[16(l/16)+b][l%16] for byte b; accumulator register r of lane l holds
+// D[4(l/16)+r][l%16].  A and B digits are read with the same lane/byte -> k
+// map, so the reduction index needs no particular order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rimp2 {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int64_t kFlushK = 65536;
+
+// Row-scaled digits of a K-contiguous FP64 matrix X[rows][K] (row stride ld):
+// D[s][row][kp] (kp = K rounded up to 64, zero padded) and exps[row].
+// One workgroup per row.
+template <int S>
+__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_t rows, int64_t K, int64_t ld,
+                                                         int8_t* D, int64_t kp, int32_t* exps, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  const int64_t row = blockIdx.x;
+  const double* x = X + row * ld;
+  __shared__ double sm[256];
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < K; k += 256) mx = fmax(mx, fabs(x[k]));
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  mx = sm[0];
+  const int e = (mx > 0.0) ? ilogb(mx) + 1 : 0;
+  if (threadIdx.x == 0) exps[row] = e;
+  for (int64_t k = threadIdx.x; k < kp; k += 256) {
+    double y = (k < K) ? ldexp(x[k], 6 - e) : 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double d = rint(y);
+      D[((int64_t)s * rows + row) * kp + k] = (int8_t)d;
+      y = (y - d) * 128.0;
+    }
+  }
+}
+
+// Column maxima of X[K][N] (row stride ld) as IEEE bit patterns (non-negative
+// doubles order like their bit patterns, so an integer max is exact and
+// order-independent).  cmax must start at zero.
+__global__ __launch_bounds__(256) void colmax_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
+                                                     unsigned long long* cmax, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int64_t k0 = (int64_t)blockIdx.y * 1024, k1 = min(K, k0 + 1024);
+  double mx = 0.0;
+  for (int64_t k = k0; k < k1; ++k) mx = fmax(mx, fabs(X[k * ld + n]));
+  atomicMax(cmax + n, (unsigned long long)__double_as_longlong(mx));
+}
+
+// Column-scaled digits of X[K][N], written transposed: D[s][n][kp], exps[n].
+// 32 x 32 tiles through LDS so both the read and the write are coalesced.
+template <int S>
+__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
+                                                         const unsigned long long* cmax, int8_t* D, int64_t kp,
+                                                         int32_t* exps, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  __shared__ double tile[32][33];
+  const int64_t k0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t k = k0 + ty + 8 * r, n = n0 + tx;
+    tile[ty + 8 * r][tx] = (k < K && n < N) ? X[k * ld + n] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t n = n0 + ty + 8 * r, k = k0 + tx;
+    if (n >= N || k >= kp) continue;
+    const double mx = __longlong_as_double((long long)cmax[n]);
+    const int e = (mx > 0.0) ? ilogb(mx) + 1 : 0;
+    if (k == 0) exps[n] = e;
+    double y = ldexp(tile[tx][ty + 8 * r], 6 - e);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double d = rint(y);
+      D[((int64_t)s * N + n) * kp + k] = (int8_t)d;
+      y = (y - d) * 128.0;
+    }
+  }
+}
+
+struct OzParams {
+  int64_t M, N, kp;            // kp: padded reduction length (multiple of 64)
+  const int8_t* A;             // digits [S][a_rows][kp]; output rows m use A row a_row0 + m
+  int64_t a_slice, a_row0;
+  const int8_t* B;             // digits [S][b_rows][kp]
+  int64_t b_slice;
+  const int32_t* ea;           // exponents of A rows (indexed like A rows)
+  const int32_t* eb;
+  double* C;
+  int64_t ldc;
+  int32_t tiles_m, tiles_n, group_m;
+  const int32_t* status;
+};
+
+// 256 threads = 4 waves in 2 x 2; workgroup tile 64 x 64, wave tile 32 x 32
+// (2 x 2 MFMA blocks); all S digit slices of a 64-wide reduction step staged
+// in LDS (double buffered, 80-byte row pitch: conflict-free 16-byte reads).
+template <int S>
+__global__ __launch_bounds__(256, 1) void gemm_oz8_kernel(OzParams p) {
+  if (p.status != nullptr && *p.status != 0) return;
+  constexpr int TM = 64, TN = 64, PITCH = 80, ROWS = TM + TN;
+  constexpr int STAGE = S * ROWS * PITCH;                     // bytes per stage
+  constexpr int NLOAD = S * ROWS * 4;                         // 16-byte pieces per stage
+  constexpr int PER = (NLOAD + 255) / 256;
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int wl = xcd_remap(blockIdx.x, gridDim.x);
+  const int gsz = p.group_m * p.tiles_n, grp = wl / gsz, first_m = grp * p.group_m;
+  const int gm = min(p.group_m, p.tiles_m - first_m), tin = wl - grp * gsz;
+  const int64_t m0 = (int64_t)(first_m + tin % gm) * TM, n0 = (int64_t)(tin / gm) * TN;
+
+  // loader: piece q -> (slice s, tile row r, 16-byte column c)
+  const int8_t* src[PER];
+  int dst[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = tid + 256 * u;
+    const int s = q / (ROWS * 4), rem = q - s * ROWS * 4, r = rem >> 2, c = rem & 3;
+    if (q < NLOAD) {
+      const int8_t* base;
+      if (r < TM) base = p.A + s * p.a_slice + (p.a_row0 + min(m0 + r, p.M - 1)) * p.kp;
+      else base = p.B + s * p.b_slice + min(n0 + (r - TM), p.N - 1) * p.kp;
+      src[u] = base + 16 * c;
+      dst[u] = (s * ROWS + r) * PITCH + 16 * c;
+    } else {
+      src[u] = nullptr;
+      dst[u] = -1;
+    }
+  }
+  v4i reg[PER];
+  auto gload = [&](int64_t k) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (dst[u] >= 0) reg[u] = *(const v4i*)(src[u] + k);
+  };
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (dst[u] >= 0) *(v4i*)(lds[b] + dst[u]) = reg[u];
+  };
+
+  v4i acc[S][2][2];
+  double out[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  auto zero_acc = [&]() {
+#pragma unroll
+    for (int L = 0; L < S; ++L)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[L][i][j] = v4i{0, 0, 0, 0};
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = 0.0;
+#pragma unroll
+          for (int L = S - 1; L >= 0; --L) v = v * (1.0 / 128.0) + (double)acc[L][i][j][r];
+          out[i][j][r] += v;
+        }
+    zero_acc();
+  };
+  zero_acc();
+
+  const int nsteps = (int)(p.kp / 64);
+  const int flush_every = (int)(kFlushK / 64);
+  if (nsteps > 0) {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+      const int b = st & 1;
+      if (st + 1 < nsteps) gload((int64_t)(st + 1) * 64);
+      const int8_t* L0 = lds[b];
+      v4i fa[S][2], fb[S][2];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          fa[s][i] = *(const v4i*)(L0 + (s * ROWS + wm * 32 + 16 * i + l16) * PITCH + 16 * g);
+          fb[s][i] = *(const v4i*)(L0 + (s * ROWS + TM + wn * 32 + 16 * i + l16) * PITCH + 16 * g);
+        }
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int t = 0; t < S - s; ++t)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
+      if (st + 1 < nsteps) sstore(b ^ 1);
+      if ((st + 1) % flush_every == 0) flush();
+      __syncthreads();
+    }
+  }
+  flush();
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 32 + 16 * i + 4 * g + r, n = n0 + wn * 32 + 16 * j + l16;
+        if (m < p.M && n < p.N)
+          p.C[m * p.ldc + n] = ldexp(out[i][j][r], p.ea[p.a_row0 + m] + p.eb[n] - 12);
+      }
+}
+
+}  // namespace rimp2

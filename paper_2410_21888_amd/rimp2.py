@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librimp2.so")
 
 RIMP2_OK, RIMP2_EINVAL, RIMP2_ENOMEM, RIMP2_EWORKSPACE = 0, -1, -2, -3
 RIMP2_EDEVICE, RIMP2_EGAP, RIMP2_ENOTSUP = -4, -5, -6
-FP64, SPLIT_BF16 = 0, 1
+FP64, SPLIT_INT8 = 0, 1
 WANT_GAMMA, WANT_DENSITY = 1, 2
 
 
@@ -32,7 +32,7 @@ class Opts(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("split_slices", ctypes.c_int32),
         ("slab_group", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("split_slices_gamma", ctypes.c_int32),
         ("slab_budget_bytes", ctypes.c_size_t),
         ("pair_skip", ctypes.c_void_p),
     ]
@@ -102,9 +102,10 @@ def version() -> int:
 
 
 def make_opts(precision: int = FP64, split_slices: int = 0, slab_group: int = 0, slab_budget_bytes: int = 0,
-              pair_skip: Optional[torch.Tensor] = None) -> Opts:
+              pair_skip: Optional[torch.Tensor] = None, split_slices_gamma: int = 0) -> Opts:
     o = Opts()
     o.precision, o.split_slices, o.slab_group = precision, split_slices, slab_group
+    o.split_slices_gamma = split_slices_gamma
     o.slab_budget_bytes = slab_budget_bytes
     o.pair_skip = pair_skip.data_ptr() if pair_skip is not None else None
     return o

@@ -1,0 +1,69 @@
+"""Split-precision path (INT8 digit products, Ozaki scheme) against the CPU oracle.
+
+Bar: |dE| <= 1 uEh (exact evaluation of the (hi, lo) pairs) and relative
+Frobenius error <= 1e-8 for Gamma, P_ij and P_ab, with the default digit
+counts (7 for (ia|jb), 5 for Gamma).  The error must also fall steeply with
+the number of digits (about 2^-7 per digit).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rimp2_oracle as O
+import paper_2410_21888_amd as rm
+from gpu_util import to_dev, rel_fro, energy_error, say
+
+pytestmark = pytest.mark.gpu
+
+
+def split_opts(sv=0, sg=0, g=0):
+    return rm.make_opts(precision=rm.SPLIT_INT8, split_slices=sv, split_slices_gamma=sg, slab_group=g)
+
+
+def check(f, opts, e_tol=1e-6, rel_tol=1e-8):
+    B, eo, ev = f.arrays()
+    say("split case nocc=%d nvir=%d naux=%d" % (f.nocc, f.nvir, f.naux))
+    r = rm.fragment(*to_dev(B, eo, ev), opts=opts)
+    ref = O.fragment(B, eo, ev)
+    dE = energy_error(r.E, ref["E_hi"], ref["E_lo"])
+    assert dE <= e_tol, dE
+    for key, got in (("Gamma", r.Gamma), ("P_ij", r.P_ij), ("P_ab", r.P_ab), ("e_pair", r.e_pair)):
+        err = rel_fro(got.cpu().numpy(), ref[key])
+        assert err <= rel_tol, (key, err)
+    return dE
+
+
+def test_split_small_workload():
+    check(synth.SMALL, split_opts())
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 17, 33), (5, 70, 130), (2, 129, 65)])
+def test_split_ragged(shape):
+    nocc, nvir, naux = shape
+    check(synth.random_fragment(nocc, nvir, naux, seed=sum(shape) + 3), split_opts(g=2))
+
+
+def test_split_error_falls_with_digits():
+    f = synth.random_fragment(6, 60, 200, seed=21)
+    B, eo, ev = f.arrays()
+    ref = O.fragment(B, eo, ev, gamma=True, density=False)
+    dB, deo, dev_ = to_dev(B, eo, ev)
+    errs = []
+    for s in (3, 4, 5, 6, 7):
+        r = rm.fragment(dB, deo, dev_, density=False, opts=split_opts(sv=s, sg=s))
+        errs.append((energy_error(r.E, ref["E_hi"], ref["E_lo"]) / abs(ref["E_hi"]),
+                     rel_fro(r.Gamma.cpu().numpy(), ref["Gamma"])))
+        say("digits %d: rel dE %.3e, Gamma %.3e" % (s, errs[-1][0], errs[-1][1]))
+    for (e0, g0), (e1, g1) in zip(errs, errs[1:]):
+        assert g1 < g0 / 20 or g1 < 1e-14
+        assert e1 < e0 / 4 or e1 < 1e-14   # E partly cancels: noisier than Gamma
+
+
+def test_split_deterministic():
+    f = synth.random_fragment(4, 50, 90, seed=31)
+    d = to_dev(*f.arrays())
+    r1 = rm.fragment(*d, opts=split_opts())
+    r2 = rm.fragment(*d, opts=split_opts())
+    for a, b in zip(r1, r2):
+        assert torch.equal(a, b)
