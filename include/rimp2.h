@@ -148,10 +148,43 @@ typedef struct {
 
 /*
  * Many independent fragments (the monomers, dimers and trimers of an MBE3
- * step).  `descs` is a HOST array of nfrag descriptors.  Fragments are run
- * largest first.  status_dev (device, [nfrag] int32, may be NULL) receives
- * each fragment's device status (RIMP2_OK or RIMP2_EGAP).  The workspace must
- * be at least rimp2_batch_workspace_size() bytes for the same descriptors.
+ * step; Sec. "Molecular Fragmentation", Eq. mbe3, and the largest-first
+ * ordering of Sec. "Asynchronous time steps").
+ *
+ * Planning (rimp2_batch_create) sorts the fragments largest first (by FLOPs).
+ * A fragment whose whole slab (all its occupied pairs) fits the wave budget
+ * (opts->slab_budget_bytes, default 64 GiB) is packed into a wave; each step
+ * of a wave -- gap check, (ia|jb), amplitudes, Gamma, P_ab, P_ij, reductions,
+ * E -- is ONE grouped launch over all of its fragments (the GEMMs are
+ * persistent launches whose workgroups take (fragment, tile) items from a
+ * counter, largest fragment first).  Larger fragments run alone, as
+ * rimp2_fragment does.  Only FP64 is supported (opts->precision must be
+ * RIMP2_FP64; pair_skip must be NULL).
+ *
+ *   descs    HOST array of nfrag descriptors; the handle keeps a copy, and the
+ *            device buffers they name must stay valid while the handle is used
+ *   *batch   receives the handle
+ *   *workspace_bytes  receives the workspace size rimp2_batch_run needs
+ *
+ * rimp2_batch_run enqueues the whole batch on `stream` without host
+ * synchronisation: it copies the handle's tables (pinned host memory written
+ * once by rimp2_batch_create) into the workspace with hipMemcpyAsync and then
+ * launches only kernels, so the call can be captured into a hipGraph and the
+ * graph replayed while the handle lives.  status_dev (device, [nfrag] int32,
+ * may be NULL) receives each fragment's status (RIMP2_OK or RIMP2_EGAP).
+ */
+typedef struct rimp2_batch_s* rimp2_batch;
+int rimp2_batch_create(int32_t nfrag, const rimp2_frag_desc* descs, const rimp2_opts* opts,
+                       rimp2_batch* batch, size_t* workspace_bytes);
+int rimp2_batch_run(rimp2_batch batch, int32_t* status_dev, void* workspace,
+                    size_t workspace_bytes, void* stream);
+int rimp2_batch_destroy(rimp2_batch batch);
+
+/*
+ * One-shot convenience over the calls above: plans, synchronises `stream`
+ * once, uploads the tables synchronously and enqueues the batch (the host
+ * tables are freed before returning).  rimp2_batch_workspace_size returns the
+ * workspace it needs for the same descriptors and options.
  */
 int rimp2_batch_workspace_size(int32_t nfrag, const rimp2_frag_desc* descs,
                                const rimp2_opts* opts, size_t* bytes);

@@ -69,10 +69,36 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 // ROLE only gives each contraction its own kernel symbol (profiler names).
 enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3 };
 
-template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI>
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
+// Decodes logical tile index t (< tiles of one split) into (tm, tn):
+// triangular order (TRI) or groups of group_m m-tiles.
+template <bool TRI>
+__device__ __forceinline__ void decode_tile(const GemmParams& p, int t, int& tm, int& tn) {
+  if (TRI) {
+    tm = 0;
+    while (t >= p.tiles_m - tm) { t -= p.tiles_m - tm; ++tm; }
+    tn = tm + t;
+  } else {
+    const int gsz = p.group_m * p.tiles_n;
+    const int grp = t / gsz;
+    const int first_m = grp * p.group_m;
+    const int gm = min(p.group_m, p.tiles_m - first_m);
+    const int tin = t - grp * gsz;
+    tm = first_m + tin % gm;
+    tn = tin / gm;
+  }
+}
+
+template <int BM, int BN, int BK>
+struct GemmLds {
+  double a[2][BK * (BM + 2)];
+  __attribute__((aligned(16))) double b[2][BK * (BN + 2)];
+};
+
+// One output tile (tm, tn) of split z.  Ends with a workgroup barrier, so the
+// LDS can be reused by the next tile.
+template <int BM, int BN, int BK, bool B_NCONTIG, bool VEC, bool TRI>
+__device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, int z, GemmLds<BM, BN, BK>& lds) {
   static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 8 == 0, "tile shape");
-  if (p.status != nullptr && *p.status != 0) return;
   typedef double d2 __attribute__((ext_vector_type(2)));
 
   constexpr int LDA = BM + 2, LDB = BN + 2;
@@ -87,35 +113,11 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
   static_assert(!B_NCONTIG || (256 % NP == 0 && BK % NSTEP == 0), "N loader shape");
   constexpr int BREG = B_NCONTIG ? BNN : BKN;
 
-  __shared__ double As[2][BK * LDA];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BK * LDB];
+  auto& As = lds.a;
+  auto& Bs = lds.b;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-
-  // logical workgroup -> (split, tile); tiles grouped group_m m-tiles wide
-  const int wl = xcd_remap(blockIdx.x, gridDim.x);
-  int tm, tn, z;
-  if (TRI) {
-    // upper-triangular tiles (tm <= tn) of a tiles_m x tiles_m grid, row by row
-    const int ntri = p.tiles_m * (p.tiles_m + 1) / 2;
-    z = wl / ntri;
-    int t = wl - z * ntri;
-    tm = 0;
-    while (t >= p.tiles_m - tm) { t -= p.tiles_m - tm; ++tm; }
-    tn = tm + t;
-  } else {
-    const int ntiles = p.tiles_m * p.tiles_n;
-    z = wl / ntiles;
-    const int t = wl - z * ntiles;
-    const int gsz = p.group_m * p.tiles_n;
-    const int grp = t / gsz;
-    const int first_m = grp * p.group_m;
-    const int gm = min(p.group_m, p.tiles_m - first_m);
-    const int tin = t - grp * gsz;
-    tm = first_m + tin % gm;
-    tn = tin / gm;
-  }
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 
   const int64_t kbeg = (int64_t)z * p.kchunk;
@@ -258,6 +260,59 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
           if (TRI && tm != tn) C[n * p.ldc + m] = acc[i][j][r];
         }
       }
+}
+
+
+// One workgroup per (split, tile); the hardware id is remapped XCD-aware.
+template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI>
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
+  if (p.status != nullptr && *p.status != 0) return;
+  __shared__ GemmLds<BM, BN, BK> lds;
+  const int wl = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = TRI ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  const int z = wl / ntiles;
+  int tm, tn;
+  decode_tile<TRI>(p, wl - z * ntiles, tm, tn);
+  gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI>(p, tm, tn, z, lds);
+}
+
+// Persistent grouped launch over many independent GEMMs (one per fragment):
+// problem f owns work items [prefix[f], prefix[f+1]) = its tiles x splits,
+// problems ordered largest first.  Each workgroup takes items from *counter
+// (which must be zero at launch) until all are taken; no workgroup waits on
+// another, so every one exits.
+struct GemmGroup {
+  const GemmParams* probs;
+  const int64_t* prefix;   // [nprob + 1]
+  int32_t nprob;
+  unsigned long long* counter;
+};
+
+template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI>
+__global__ __launch_bounds__(256, 2) void gemm_f64_grouped(GemmGroup G) {
+  __shared__ GemmLds<BM, BN, BK> lds;
+  __shared__ long long item;
+  const long long total = G.prefix[G.nprob];
+  for (;;) {
+    if (threadIdx.x == 0) item = (long long)atomicAdd(G.counter, 1ull);
+    __syncthreads();
+    const long long t = item;
+    __syncthreads();
+    if (t >= total) break;
+    int lo = 0, hi = G.nprob - 1;   // last f with prefix[f] <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (G.prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const GemmParams p = G.probs[lo];
+    if (p.status != nullptr && *p.status != 0) continue;
+    const int u = (int)(t - G.prefix[lo]);
+    const int ntiles = TRI ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+    const int z = u / ntiles;
+    int tm, tn;
+    decode_tile<TRI>(p, u - z * ntiles, tm, tn);
+    gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI>(p, tm, tn, z, lds);
+  }
 }
 
 }  // namespace rimp2

@@ -53,8 +53,8 @@ __device__ __forceinline__ void block_dd_reduce(double& hi, double& lo) {
 // ((eps_i + eps_j) - eps_a) - eps_b is negative.  FP addition is monotone, so
 // it is enough that the largest one, built from max eps_occ and min eps_vir
 // in the same order, is negative.  A NaN anywhere also fails.  One workgroup.
-__global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int nocc, const double* ev, int nvir,
-                                                        int32_t* status) {
+__device__ __forceinline__ void gap_check_block(const double* eo, int nocc, const double* ev, int nvir,
+                                                int32_t* status) {
   __shared__ double smax[256], smin[256];
   __shared__ int snan[256];
   const int t = threadIdx.x;
@@ -78,6 +78,11 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
   }
 }
 
+__global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int nocc, const double* ev, int nvir,
+                                                        int32_t* status) {
+  gap_check_block(eo, nocc, ev, nvir, status);
+}
+
 // Amplitude pass over one slab group.
 // V/X slab: element (kk, a, j, b) at S[((kk*nvir + a)*nocc + j)*nvir + b], kk < g.
 // One workgroup per occupied pair (k = k0 + kk, j).  For each pair of 32x32
@@ -88,13 +93,11 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
 // e_kj = sum_ab T[a,b] V[a,b] with compensated per-thread sums and a fixed
 // reduction order.  pair_skip (may be null) zeroes skipped pairs.
 constexpr int AT = 32;
-__global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
-                                                        int nocc, int nvir, int k0, int energy_only,
-                                                        const uint8_t* pair_skip, double* e_pair,
-                                                        const int32_t* status) {
-  if (*status != 0) return;
+__device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
+                                                int nvir, int k0, int energy_only, const uint8_t* pair_skip,
+                                                double* e_pair, int kk, int j) {
   __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];
-  const int kk = blockIdx.x / nocc, j = blockIdx.x - kk * nocc, k = k0 + kk;
+  const int k = k0 + kk;
   const int64_t ld = (int64_t)nocc * nvir;
   double* blk = S + ((int64_t)kk * nvir * nocc + j) * nvir;  // element (a,b) at blk[a*ld + b]
   double* tblk = Tslab + ((int64_t)kk * nvir * nocc + j) * nvir;
@@ -161,13 +164,20 @@ __global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab
   if (t == 0) e_pair[(int64_t)k * nocc + j] = h + l;
 }
 
+__global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
+                                                        int nocc, int nvir, int k0, int energy_only,
+                                                        const uint8_t* pair_skip, double* e_pair,
+                                                        const int32_t* status) {
+  if (*status != 0) return;
+  const int kk = blockIdx.x / nocc, j = blockIdx.x - kk * nocc;
+  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, energy_only, pair_skip, e_pair, kk, j);
+}
+
 // out[m*ldo + n] = (accumulate ? out : 0) + alpha * sum_{z < splits} W[z*zs + m*ldw + n],
 // summed in increasing z.
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(double* out, int64_t ldo, const double* W, int64_t ldw,
-                                                            int64_t zs, int splits, int64_t M, int64_t N, double alpha,
-                                                            int accumulate, const int32_t* status) {
-  if (*status != 0) return;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void splitk_reduce_at(double* out, int64_t ldo, const double* W, int64_t ldw, int64_t zs,
+                                                 int splits, int64_t M, int64_t N, double alpha, int accumulate,
+                                                 int64_t idx) {
   if (idx >= M * N) return;
   const int64_t m = idx / N, n = idx - m * N;
   double s = 0.0;
@@ -176,10 +186,15 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(double* out, int64_t
   *o = (accumulate ? *o : 0.0) + alpha * s;
 }
 
-// E = sum of count values, compensated, fixed order; writes (hi, lo).
-__global__ __launch_bounds__(256) void energy_sum_kernel(const double* e, int64_t count, double* E,
-                                                         const int32_t* status) {
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(double* out, int64_t ldo, const double* W, int64_t ldw,
+                                                            int64_t zs, int splits, int64_t M, int64_t N, double alpha,
+                                                            int accumulate, const int32_t* status) {
   if (*status != 0) return;
+  splitk_reduce_at(out, ldo, W, ldw, zs, splits, M, N, alpha, accumulate, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// E = sum of count values, compensated, fixed order; writes (hi, lo).
+__device__ __forceinline__ void energy_sum_block(const double* e, int64_t count, double* E) {
   double sh = 0.0, sl = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += 256) {
     double s, err;
@@ -196,6 +211,12 @@ __global__ __launch_bounds__(256) void energy_sum_kernel(const double* e, int64_
     E[0] = hi;
     E[1] = lo;
   }
+}
+
+__global__ __launch_bounds__(256) void energy_sum_kernel(const double* e, int64_t count, double* E,
+                                                         const int32_t* status) {
+  if (*status != 0) return;
+  energy_sum_block(e, count, E);
 }
 
 // status_out[idx] = *status (per-fragment status of a batch).

@@ -25,6 +25,7 @@
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
 #include "split_int8.hpp"
+#include "batch.hpp"
 
 using namespace rimp2;
 
@@ -441,6 +442,316 @@ int want_of(const double* Gam, const double* Pij, const double* Pab, int* want) 
   return RIMP2_OK;
 }
 
+
+// ---- batches -----------------------------------------------------------------
+struct GemmList {            // grouped GEMM problems of one role in one wave
+  std::vector<GemmParams> p;
+  std::vector<int64_t> prefix;  // work items (tiles x splits)
+};
+struct Wave {
+  std::vector<int32_t> frags;   // original fragment indices, largest first
+  size_t tab_bytes = 0;         // bytes of device tables at the start of the wave region
+  size_t host_off = 0;          // offset of this wave's tables in the pinned blob
+  size_t bytes = 0;             // tables + fragment partitions
+  // offsets within the tables
+  size_t o_fs, o_idx, o_amp, o_amp_pre, o_red, o_red_pre, o_cnt;
+  size_t o_g[8], o_pre[8];      // GEMM lists: ints v/nv, gamma v/nv, pab v/nv, pij v/nv
+  int n_g[8];
+  int64_t items_g[8];
+  int namp, nred_ab, nred_ij;
+  int64_t amp_blocks, red_blocks_ab, red_blocks_ij;
+};
+}  // namespace
+
+struct rimp2_batch_s {
+  std::vector<rimp2_frag_desc> d;
+  std::vector<int32_t> solo;       // fragments run alone
+  std::vector<Plan> plan;          // per fragment (solo: own plan; grouped: full-slab plan)
+  std::vector<Wave> waves;
+  std::vector<char> blob;          // tables of every wave, as laid out at the start of the workspace
+  char* host = nullptr;            // pinned copy of blob (handle path)
+  size_t tables_total = 0, ws_bytes = 0;
+};
+
+namespace {
+
+uint64_t rel(size_t off) { return kRelTag | (uint64_t)off; }
+template <class T>
+T* relp(size_t off) { return (T*)(uintptr_t)rel(off); }
+bool aligned16(const void* p) { return ((uintptr_t)p & ~kRelTag) % 16 == 0; }
+bool kop_vec_rel(const KOperand& o, int64_t K) {
+  const bool plain = o.kdiv >= K;
+  return aligned16(o.base) && o.rs % 2 == 0 && (plain || (o.kdiv % 2 == 0 && o.ks1 % 2 == 0));
+}
+
+// tiles, splits and group size of a GEMM, as launch_gemm sets them
+int64_t finalize_gemm(GemmParams& gp, int BM, int BN, bool tri) {
+  gp.tiles_m = (int32_t)cdiv(gp.M, BM);
+  gp.tiles_n = (int32_t)cdiv(gp.N, BN);
+  gp.group_m = 8;
+  if (gp.kchunk <= 0) gp.kchunk = gp.K;
+  gp.kchunk = cdiv(gp.kchunk, kBK) * kBK;
+  gp.splits = (int32_t)cdiv(gp.K, gp.kchunk);
+  const int64_t tiles = tri ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
+  return tiles * gp.splits;
+}
+
+size_t place(size_t& off, size_t bytes) {
+  const size_t o = off;
+  off = align_up(off + bytes);
+  return o;
+}
+
+int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, rimp2_batch_s* B) {
+  if (nfrag < 0 || (nfrag > 0 && !d)) return fail(RIMP2_EINVAL, "bad batch arguments");
+  if (opts && opts->precision != RIMP2_FP64) return fail(RIMP2_ENOTSUP, "batches run in FP64 only");
+  if (opts && opts->pair_skip) return fail(RIMP2_ENOTSUP, "pair_skip is not supported for batches");
+  B->d.assign(d, d + nfrag);
+  B->plan.resize(nfrag);
+  const size_t budget = (opts && opts->slab_budget_bytes) ? opts->slab_budget_bytes : (size_t)64 << 30;
+  std::vector<int32_t> order(nfrag), grouped;
+  std::vector<char> solo(nfrag, 0);
+  for (int32_t f = 0; f < nfrag; ++f) {
+    if (!d[f].B || !d[f].eps_occ || !d[f].eps_vir || !d[f].E)
+      return fail(RIMP2_EINVAL, "fragment %d: B, eps_occ, eps_vir and E must not be NULL", f);
+    int want, rc;
+    if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return fail(rc, "fragment %d: %s", f, g_err);
+    rimp2_opts o{};
+    o.slab_group = d[f].nocc;     // whole slab
+    Plan P;
+    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, &o, &P)))
+      return fail(rc, "fragment %d: %s", f, g_err);
+    P.s_gam = 1;
+    if (P.total > budget) {
+      solo[f] = 1;
+      if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &P)))
+        return fail(rc, "fragment %d: %s", f, g_err);
+    }
+    B->plan[f] = P;
+    order[f] = f;
+  }
+  auto cost = [&](int32_t f) { return (double)d[f].nocc * d[f].nocc * d[f].nvir * d[f].nvir * d[f].naux; };
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  size_t ws = kAlign, max_solo = 0;
+  for (int32_t f : order) {
+    if (solo[f]) { B->solo.push_back(f); max_solo = std::max(max_solo, B->plan[f].total); }
+    else grouped.push_back(f);
+  }
+  // pack waves greedily (largest first) by the sum of full-slab plans
+  for (size_t i = 0; i < grouped.size();) {
+    Wave W;
+    size_t sum = 0;
+    while (i < grouped.size() && (W.frags.empty() || sum + B->plan[grouped[i]].total <= budget)) {
+      sum += B->plan[grouped[i]].total;
+      W.frags.push_back(grouped[i++]);
+    }
+    B->waves.push_back(W);
+  }
+  // table layout of every wave (sizes depend only on the wave's fragment count)
+  size_t tab = 0;
+  for (Wave& W : B->waves) {
+    const int n = (int)W.frags.size();
+    size_t t = 0;
+    W.o_fs = place(t, sizeof(FragSmall) * n);
+    W.o_idx = place(t, sizeof(int32_t) * n);
+    W.o_amp = place(t, sizeof(AmpDesc) * n);
+    W.o_amp_pre = place(t, sizeof(int64_t) * (n + 1));
+    W.o_red = place(t, sizeof(ReduceDesc) * 2 * n);
+    W.o_red_pre = place(t, sizeof(int64_t) * (2 * n + 1));
+    for (int r = 0; r < 8; ++r) {
+      W.o_g[r] = place(t, sizeof(GemmParams) * n);
+      W.o_pre[r] = place(t, sizeof(int64_t) * (n + 1));
+    }
+    W.o_cnt = place(t, 8 * sizeof(unsigned long long));
+    W.tab_bytes = t;
+    W.host_off = tab;
+    tab = align_up(tab + t);
+  }
+  B->tables_total = tab;
+  B->blob.assign(tab, 0);
+  for (Wave& W : B->waves) {
+    const int n = (int)W.frags.size();
+    std::vector<FragSmall> fs(n);
+    std::vector<int32_t> idx(n);
+    std::vector<AmpDesc> amp(n);
+    std::vector<int64_t> amp_pre(n + 1, 0);
+    std::vector<ReduceDesc> red;
+    std::vector<int64_t> red_pre(1, 0);
+    GemmList gl[8];
+    for (auto& l : gl) l.prefix.assign(1, 0);
+    size_t poff = tab;   // fragment partitions follow all tables (shared by the waves)
+    for (int i = 0; i < n; ++i) {
+      const int32_t f = W.frags[i];
+      const rimp2_frag_desc& q = d[f];
+      const Plan& P = B->plan[f];
+      const size_t base = poff;
+      poff = align_up(poff + P.total);
+      const int64_t nocc = q.nocc, nvir = q.nvir, naux = q.naux, L = nocc * nvir;
+      int32_t* status = relp<int32_t>(base + P.off_status);
+      double* V = relp<double>(base + P.off_V);
+      double* T = relp<double>(base + P.off_T);
+      double* ep = q.e_pair ? q.e_pair : relp<double>(base + P.off_e);
+      fs[i] = FragSmall{q.eps_occ, q.eps_vir, ep, q.E, status, q.nocc, q.nvir};
+      idx[i] = f;
+      amp[i] = AmpDesc{V, T, q.eps_occ, q.eps_vir, ep, status, q.nocc, q.nvir, (P.gamma || P.density) ? 0 : 1, 0};
+      amp_pre[i + 1] = amp_pre[i] + nocc * nocc;
+      {  // (ia|jb)
+        GemmParams gp{};
+        gp.M = nocc * nvir; gp.N = L; gp.K = naux; gp.kchunk = naux;
+        gp.A = KOperand{q.B, naux, INT64_MAX, 0};
+        gp.Bk = KOperand{q.B, naux, INT64_MAX, 0};
+        gp.C = V; gp.ldc = L; gp.status = status;
+        const int64_t items = finalize_gemm(gp, kTile, kTile, false);
+        const int r = (kop_vec_rel(gp.A, gp.K) && kop_vec_rel(gp.Bk, gp.K)) ? 0 : 1;
+        gl[r].p.push_back(gp); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+      }
+      if (P.gamma) {
+        GemmParams gp{};
+        gp.M = nocc * nvir; gp.N = naux; gp.K = L; gp.kchunk = L;
+        gp.A = KOperand{T, L, INT64_MAX, 0};
+        gp.Bn = NOperand{q.B, naux};
+        gp.C = q.Gamma; gp.ldc = naux; gp.status = status;
+        const int64_t items = finalize_gemm(gp, kTile, kTile, false);
+        const int r = (kop_vec_rel(gp.A, gp.K) && aligned16(q.B) && naux % 2 == 0) ? 2 : 3;
+        gl[r].p.push_back(gp); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+      }
+      if (P.density) {
+        double* Wab = relp<double>(base + P.off_pab);
+        double* Wij = relp<double>(base + P.off_pij);
+        GemmParams ga{};
+        ga.M = nvir; ga.N = nvir; ga.K = nocc * L; ga.kchunk = cdiv(ga.K, P.s_ab);
+        ga.A = KOperand{T, L, L, nvir * L};
+        ga.Bk = KOperand{V, L, L, nvir * L};
+        ga.C = Wab; ga.ldc = nvir; ga.split_stride = nvir * nvir; ga.status = status;
+        int64_t items = finalize_gemm(ga, kTile, kTile, false);
+        int r = (kop_vec_rel(ga.A, ga.K) && kop_vec_rel(ga.Bk, ga.K)) ? 4 : 5;
+        gl[r].p.push_back(ga); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        GemmParams gi{};
+        gi.M = nocc; gi.N = nocc; gi.K = nocc * nvir * nvir; gi.kchunk = cdiv(gi.K, P.s_ij);
+        gi.A = KOperand{T, nvir, nvir, L};
+        gi.Bk = KOperand{V, nvir, nvir, L};
+        gi.C = Wij; gi.ldc = nocc; gi.split_stride = nocc * nocc; gi.status = status;
+        items = finalize_gemm(gi, kSmallTile, kSmallTile, true);
+        r = (kop_vec_rel(gi.A, gi.K) && kop_vec_rel(gi.Bk, gi.K)) ? 6 : 7;
+        gl[r].p.push_back(gi); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        ReduceDesc ra{q.P_ab, Wab, status, nvir, nvir, nvir * nvir, nvir, nvir, 1.0, ga.splits, 0};
+        ReduceDesc ri{q.P_ij, Wij, status, nocc, nocc, nocc * nocc, nocc, nocc, -1.0, gi.splits, 0};
+        red.push_back(ra); red_pre.push_back(red_pre.back() + cdiv(nvir * nvir, 256));
+        red.push_back(ri); red_pre.push_back(red_pre.back() + cdiv(nocc * nocc, 256));
+      }
+    }
+    W.bytes = poff;
+    ws = std::max(ws, poff);
+    W.namp = n;
+    W.amp_blocks = amp_pre[n];
+    W.nred_ab = (int)red.size();
+    W.red_blocks_ab = red_pre.back();
+    for (int r = 0; r < 8; ++r) { W.n_g[r] = (int)gl[r].p.size(); W.items_g[r] = gl[r].prefix.back(); }
+    char* blob = B->blob.data() + W.host_off;
+    auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) memcpy(blob + off, src, bytes); };
+    put(W.o_fs, fs.data(), sizeof(FragSmall) * n);
+    put(W.o_idx, idx.data(), sizeof(int32_t) * n);
+    put(W.o_amp, amp.data(), sizeof(AmpDesc) * n);
+    put(W.o_amp_pre, amp_pre.data(), sizeof(int64_t) * (n + 1));
+    put(W.o_red, red.data(), sizeof(ReduceDesc) * red.size());
+    put(W.o_red_pre, red_pre.data(), sizeof(int64_t) * red_pre.size());
+    for (int r = 0; r < 8; ++r) {
+      put(W.o_g[r], gl[r].p.data(), sizeof(GemmParams) * gl[r].p.size());
+      put(W.o_pre[r], gl[r].prefix.data(), sizeof(int64_t) * gl[r].prefix.size());
+    }
+  }
+  // solo fragments use the workspace after all tables
+  B->ws_bytes = std::max(ws, align_up(tab + max_solo));
+  return RIMP2_OK;
+}
+
+template <int BM, int BN, bool NC, int ROLE, bool VEC, bool TRI>
+int launch_grouped(const GemmGroup& G, int64_t items, int role, hipStream_t st) {
+  if (G.nprob == 0 || items == 0) return RIMP2_OK;
+  const int64_t grid = std::min<int64_t>(items, kSlots);
+  return traced(role, 0, 0, 0, st, [&] {
+    hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, kBK, NC, ROLE, VEC, TRI>), dim3((unsigned)grid), dim3(256), 0, st, G);
+  });
+}
+
+// upload: 0 = tables already in the workspace, 1 = copy them from B->host (pinned) on the stream
+int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t bytes, hipStream_t st, int upload) {
+  if (!workspace) return fail(RIMP2_EINVAL, "workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < B->ws_bytes) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, B->ws_bytes);
+  char* ws = (char*)workspace;
+  int rc;
+  if (upload && B->tables_total) {
+    if (!B->host) return fail(RIMP2_EINVAL, "batch tables are not resident");
+    HIP_TRY(hipMemcpyAsync(ws, B->host, B->tables_total, hipMemcpyHostToDevice, st));
+  }
+  // solo fragments run with their own workspace layout after the tables
+  char* solo_ws = ws + B->tables_total;
+  for (int32_t f : B->solo) {
+    const rimp2_frag_desc& q = B->d[f];
+    if ((rc = run_fragment(B->plan[f], q.B, q.eps_occ, q.eps_vir, q.E, q.Gamma, q.P_ij, q.P_ab, q.e_pair, solo_ws,
+                           nullptr, st)))
+      return fail(rc, "fragment %d: %s", f, g_err);
+    if (status_dev && (rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
+                         hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, st,
+                                            (const int32_t*)(solo_ws + B->plan[f].off_status), status_dev, (int)f);
+                       })))
+      return rc;
+  }
+  for (const Wave& W : B->waves) {
+    const int n = (int)W.frags.size();
+    GemmParams* gp0 = (GemmParams*)(ws + W.host_off + W.o_g[0]);
+    auto at = [&](size_t o) { return ws + W.host_off + o; };
+    if ((rc = traced(R_STATUS, 0, 0, 0, st, [&] {
+           // relocate every table (GEMM lists are contiguous per role; relocate each list)
+           for (int r = 0; r < 8; ++r)
+             if (W.n_g[r])
+               hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(W.n_g[r], 256)), dim3(256), 0, st, ws,
+                                  (GemmParams*)at(W.o_g[r]), W.n_g[r], (AmpDesc*)nullptr, 0, (ReduceDesc*)nullptr, 0,
+                                  (FragSmall*)nullptr, 0);
+           const int m = std::max(n, W.nred_ab);
+           hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, ws, gp0, 0,
+                              (AmpDesc*)at(W.o_amp), n, (ReduceDesc*)at(W.o_red), W.nred_ab, (FragSmall*)at(W.o_fs),
+                              n);
+           hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt), 8);
+           hipLaunchKernelGGL(gap_check_grouped, dim3((unsigned)n), dim3(256), 0, st, (const FragSmall*)at(W.o_fs));
+         })))
+      return rc;
+    auto grp = [&](int r) {
+      return GemmGroup{(const GemmParams*)at(W.o_g[r]), (const int64_t*)at(W.o_pre[r]), W.n_g[r],
+                       (unsigned long long*)at(W.o_cnt) + r};
+    };
+    if ((rc = launch_grouped<kTile, kTile, false, ROLE_INTS, true, false>(grp(0), W.items_g[0], R_INTS, st))) return rc;
+    if ((rc = launch_grouped<kTile, kTile, false, ROLE_INTS, false, false>(grp(1), W.items_g[1], R_INTS, st))) return rc;
+    if ((rc = traced(R_AMP, 0, 0, 0, st, [&] {
+           hipLaunchKernelGGL(amplitude_grouped, dim3((unsigned)W.amp_blocks), dim3(256), 0, st,
+                              (const AmpDesc*)at(W.o_amp), (const int64_t*)at(W.o_amp_pre), n);
+         })))
+      return rc;
+    if ((rc = launch_grouped<kTile, kTile, true, ROLE_GAMMA, true, false>(grp(2), W.items_g[2], R_GAMMA, st))) return rc;
+    if ((rc = launch_grouped<kTile, kTile, true, ROLE_GAMMA, false, false>(grp(3), W.items_g[3], R_GAMMA, st))) return rc;
+    if ((rc = launch_grouped<kTile, kTile, false, ROLE_PAB, true, false>(grp(4), W.items_g[4], R_PAB, st))) return rc;
+    if ((rc = launch_grouped<kTile, kTile, false, ROLE_PAB, false, false>(grp(5), W.items_g[5], R_PAB, st))) return rc;
+    if ((rc = launch_grouped<kSmallTile, kSmallTile, false, ROLE_PIJ, true, true>(grp(6), W.items_g[6], R_PIJ, st)))
+      return rc;
+    if ((rc = launch_grouped<kSmallTile, kSmallTile, false, ROLE_PIJ, false, true>(grp(7), W.items_g[7], R_PIJ, st)))
+      return rc;
+    if (W.nred_ab && (rc = traced(R_REDUCE, 0, 0, 0, st, [&] {
+                        hipLaunchKernelGGL(reduce_grouped, dim3((unsigned)W.red_blocks_ab), dim3(256), 0, st,
+                                           (const ReduceDesc*)at(W.o_red), (const int64_t*)at(W.o_red_pre), W.nred_ab);
+                      })))
+      return rc;
+    if ((rc = traced(R_ESUM, 0, 0, 0, st, [&] {
+           hipLaunchKernelGGL(energy_sum_grouped, dim3((unsigned)n), dim3(256), 0, st, (const FragSmall*)at(W.o_fs));
+           if (status_dev)
+             hipLaunchKernelGGL(status_copy_grouped, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st,
+                                (const FragSmall*)at(W.o_fs), (const int32_t*)at(W.o_idx), n, status_dev);
+         })))
+      return rc;
+  }
+  return RIMP2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -496,54 +807,64 @@ int rimp2_read_status(const void* workspace, void* stream, int32_t* status) {
   return RIMP2_OK;
 }
 
-int rimp2_batch_workspace_size(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, size_t* bytes) {
-  if (nfrag < 0 || (nfrag > 0 && !d) || !bytes) return fail(RIMP2_EINVAL, "bad batch arguments");
-  size_t mx = kAlign;
-  for (int32_t f = 0; f < nfrag; ++f) {
-    int want, rc;
-    if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return rc;
-    Plan P;
-    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &P)))
-      return fail(rc, "fragment %d: %s", f, g_err);
-    mx = std::max(mx, P.total);
+int rimp2_batch_create(int32_t nfrag, const rimp2_frag_desc* descs, const rimp2_opts* opts, rimp2_batch* batch,
+                       size_t* workspace_bytes) {
+  if (!batch || !workspace_bytes) return fail(RIMP2_EINVAL, "batch and workspace_bytes must not be NULL");
+  rimp2_batch_s* B = new rimp2_batch_s();
+  int rc = batch_plan(nfrag, descs, opts, B);
+  if (!rc && B->tables_total) {
+    if (hipHostMalloc((void**)&B->host, B->tables_total, hipHostMallocDefault) != hipSuccess) {
+      B->host = nullptr;
+      rc = fail(RIMP2_EDEVICE, "hipHostMalloc of %zu bytes failed", B->tables_total);
+    } else {
+      memcpy(B->host, B->blob.data(), B->tables_total);
+    }
   }
-  *bytes = mx;
+  if (rc) {
+    if (B->host) (void)hipHostFree(B->host);
+    delete B;
+    return rc;
+  }
+  *batch = B;
+  *workspace_bytes = B->ws_bytes;
   return RIMP2_OK;
 }
 
-int rimp2_fragment_batch(int32_t nfrag, const rimp2_frag_desc* d, int32_t* status_dev, void* workspace,
-                         size_t workspace_bytes, const rimp2_opts* opts, void* stream) {
-  if (nfrag < 0 || (nfrag > 0 && !d) || !workspace) return fail(RIMP2_EINVAL, "bad batch arguments");
-  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
-  std::vector<Plan> plans(nfrag);
-  std::vector<int32_t> order(nfrag);
-  for (int32_t f = 0; f < nfrag; ++f) {
-    if (!d[f].B || !d[f].eps_occ || !d[f].eps_vir || !d[f].E)
-      return fail(RIMP2_EINVAL, "fragment %d: B, eps_occ, eps_vir and E must not be NULL", f);
-    int want, rc;
-    if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return rc;
-    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &plans[f])))
-      return fail(rc, "fragment %d: %s", f, g_err);
-    if (plans[f].total > workspace_bytes)
-      return fail(RIMP2_ENOMEM, "fragment %d needs %zu workspace bytes, have %zu", f, plans[f].total, workspace_bytes);
-    order[f] = f;
-  }
-  // largest first (by FLOP count of the (ia|jb) and Gamma contractions)
-  auto cost = [&](int32_t f) { return (double)d[f].nocc * d[f].nocc * d[f].nvir * d[f].nvir * d[f].naux; };
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
-  hipStream_t st = (hipStream_t)stream;
-  for (int32_t f : order) {
-    int rc = run_fragment(plans[f], d[f].B, d[f].eps_occ, d[f].eps_vir, d[f].E, d[f].Gamma, d[f].P_ij, d[f].P_ab,
-                          d[f].e_pair, (char*)workspace, nullptr, st);
-    if (rc) return fail(rc, "fragment %d: %s", f, g_err);
-    if (status_dev) {
-      rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
-        hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, st, (const int32_t*)workspace, status_dev, (int)f);
-      });
-      if (rc) return rc;
-    }
-  }
+int rimp2_batch_run(rimp2_batch batch, int32_t* status_dev, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!batch) return fail(RIMP2_EINVAL, "batch is NULL");
+  return batch_run(batch, status_dev, workspace, workspace_bytes, (hipStream_t)stream, 1);
+}
+
+int rimp2_batch_destroy(rimp2_batch batch) {
+  if (!batch) return RIMP2_OK;
+  if (batch->host) HIP_TRY(hipHostFree(batch->host));
+  delete batch;
   return RIMP2_OK;
+}
+
+int rimp2_batch_workspace_size(int32_t nfrag, const rimp2_frag_desc* descs, const rimp2_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  rimp2_batch_s B;
+  const int rc = batch_plan(nfrag, descs, opts, &B);
+  if (rc) return rc;
+  *bytes = B.ws_bytes;
+  return RIMP2_OK;
+}
+
+int rimp2_fragment_batch(int32_t nfrag, const rimp2_frag_desc* descs, int32_t* status_dev, void* workspace,
+                         size_t workspace_bytes, const rimp2_opts* opts, void* stream) {
+  if (!workspace) return fail(RIMP2_EINVAL, "workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  rimp2_batch_s B;
+  int rc = batch_plan(nfrag, descs, opts, &B);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (workspace_bytes < B.ws_bytes)
+    return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, B.ws_bytes);
+  // earlier work on the stream may still use the workspace: wait, then upload the tables synchronously
+  HIP_TRY(hipStreamSynchronize(st));
+  if (B.tables_total) HIP_TRY(hipMemcpy(workspace, B.blob.data(), B.tables_total, hipMemcpyHostToDevice));
+  return batch_run(&B, status_dev, workspace, workspace_bytes, st, 0);
 }
 
 int rimp2_timing_enable(int enable) {

@@ -78,6 +78,13 @@ def lib():
                                                  ctypes.POINTER(sz)]
         L.rimp2_fragment_batch.restype = ctypes.c_int
         L.rimp2_fragment_batch.argtypes = [i32, ctypes.POINTER(FragDesc), vp, vp, sz, ctypes.POINTER(Opts), vp]
+        L.rimp2_batch_create.restype = ctypes.c_int
+        L.rimp2_batch_create.argtypes = [i32, ctypes.POINTER(FragDesc), ctypes.POINTER(Opts), ctypes.POINTER(vp),
+                                         ctypes.POINTER(sz)]
+        L.rimp2_batch_run.restype = ctypes.c_int
+        L.rimp2_batch_run.argtypes = [vp, vp, vp, sz, vp]
+        L.rimp2_batch_destroy.restype = ctypes.c_int
+        L.rimp2_batch_destroy.argtypes = [vp]
         L.rimp2_timing_enable.restype = ctypes.c_int
         L.rimp2_timing_enable.argtypes = [ctypes.c_int]
         L.rimp2_timing_collect.restype = ctypes.c_int
@@ -251,3 +258,34 @@ def timing_collect() -> list:
     _check(lib().rimp2_timing_collect(arr, 32, ctypes.byref(n)))
     return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms, alg_flops=a.alg_flops,
                  exec_flops=a.exec_flops, alg_bytes=a.alg_bytes) for a in arr[:n.value]]
+
+
+class Batch:
+    """A planned batch (rimp2_batch_create): run() enqueues it without host
+    synchronisation, so it can be captured into a graph and replayed while the
+    handle lives.  The tensors named in ``frags`` must stay alive."""
+
+    def __init__(self, frags: Sequence[dict], opts: Optional[Opts] = None):
+        self._frags = list(frags)
+        self._arr = _descs(self._frags)
+        h = ctypes.c_void_p(None)
+        n = ctypes.c_size_t(0)
+        _check(lib().rimp2_batch_create(len(self._frags), self._arr, ctypes.byref(opts) if opts else None,
+                                        ctypes.byref(h), ctypes.byref(n)))
+        self._h = h
+        self.workspace_bytes = n.value
+
+    def run(self, workspace: torch.Tensor, status: Optional[torch.Tensor] = None, stream=None) -> None:
+        _check(lib().rimp2_batch_run(self._h, _ptr(status), _ptr(workspace), workspace.numel(),
+                                     _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            lib().rimp2_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

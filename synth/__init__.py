@@ -31,6 +31,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "csynth.c")
 _LIB = os.path.join(_HERE, "_csynth.so")
+_DSRC = os.path.join(_HERE, "dsynth.hip")
+_DLIB = os.path.join(_HERE, "_dsynth.so")
 
 # tensor ids inside one fragment's key space
 T_B, T_EOCC, T_EVIR, T_ROCC, T_RAUX, T_SIZES = 0, 1, 2, 3, 4, 5
@@ -44,6 +46,49 @@ def build(force: bool = False) -> str:
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_device(force: bool = False) -> str:
+    """Compile the device twin of the generator (hipcc, gfx950) in place."""
+    if force or not os.path.exists(_DLIB) or os.path.getmtime(_DLIB) < os.path.getmtime(_DSRC):
+        tmp = _DLIB + ".tmp%d" % os.getpid()
+        hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-Xclang", "-target-feature",
+                               "-Xclang", "-packed-fp32-ops", "-o", tmp, _DSRC],
+                              stderr=subprocess.DEVNULL)
+        os.replace(tmp, _DLIB)
+    return _DLIB
+
+
+_dlib = None
+
+
+def three_index_device(k: int, nocc: int, nvir: int, naux: int, scale, out, i0: int = 0, i1: int | None = None,
+                       stream=None):
+    """Rows [i0, i1) of the three-index tensor generated on the GPU into the
+    torch tensor ``out`` (float64, [i1-i0][nvir][naux]); ``scale`` as in
+    three_index (numpy)."""
+    global _dlib
+    import torch
+    if _dlib is None:
+        if not os.path.exists(_DLIB):
+            raise RuntimeError("synth/_dsynth.so is not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(_DLIB)
+        lib.dsynth_three_index.restype = ctypes.c_int
+        lib.dsynth_three_index.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p]
+        _dlib = lib
+    i1 = nocc if i1 is None else i1
+    sc = torch.as_tensor(np.ascontiguousarray(scale, dtype=np.float64)).to(out.device)
+    per_i = 1 if sc.dim() == 2 else 0
+    assert out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (i1 - i0, nvir, naux)
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    rc = _dlib.dsynth_three_index(k, i0, i1, nvir, naux, sc.data_ptr(), per_i, out.data_ptr(), st)
+    if rc != 0:
+        raise RuntimeError("device generator launch failed")
+    torch.cuda.current_stream().synchronize()
+    return out
 
 
 _lib = None
@@ -147,6 +192,10 @@ class Fragment:
 
     def B(self, i0: int = 0, i1: int | None = None, out=None) -> np.ndarray:
         return three_index(self.key_B, self.nocc, self.nvir, self.naux, self.scale(), i0, i1, out)
+
+    def B_device(self, out):
+        """The whole B generated on the GPU into a torch tensor."""
+        return three_index_device(self.key_B, self.nocc, self.nvir, self.naux, self.scale(), out)
 
     def eps(self):
         return orbital_energies(self.seed, self.frag, self.nocc, self.nvir)

@@ -91,3 +91,16 @@ def test_product_path_does_not_touch_oracle():
             if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in src.lower(), fn
+
+
+def test_batch_plan_errors_and_sizes():
+    arr = (R.FragDesc * 2)()
+    for i, (o, v, x) in enumerate(((3, 10, 20), (5, 20, 40))):
+        arr[i].nocc, arr[i].nvir, arr[i].naux = o, v, x
+        arr[i].B, arr[i].eps_occ, arr[i].eps_vir, arr[i].E = 256, 512, 768, 1024
+    n = ctypes.c_size_t(0)
+    assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_OK and n.value > 0
+    split = R.make_opts(precision=rm.SPLIT_INT8)
+    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(split), ctypes.byref(n)) == rm.RIMP2_ENOTSUP
+    arr[1].nocc = 0
+    assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_EINVAL

@@ -1,0 +1,110 @@
+"""Batched fragments (grouped persistent launches, solo fragments, waves,
+graph capture) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rimp2_oracle as O
+import paper_2410_21888_amd as rm
+from gpu_util import to_dev, rel_fro, energy_error, say
+
+pytestmark = pytest.mark.gpu
+
+
+def make_frags(sizes, seed=1003, outputs=("Gamma", "P", "e_pair")):
+    frags, refs = [], []
+    for n, (nocc, nvir, naux) in enumerate(sizes):
+        f = synth.Fragment(nocc, nvir, naux, seed=seed, frag=n)
+        B, eo, ev = f.arrays()
+        refs.append(O.fragment(B, eo, ev, gamma="Gamma" in outputs, density="P" in outputs))
+        dB, deo, dev_ = to_dev(B, eo, ev)
+        kw = dict(dtype=torch.float64, device=dB.device)
+        d = dict(B=dB, eps_occ=deo, eps_vir=dev_, E=torch.zeros(2, **kw))
+        if "Gamma" in outputs:
+            d["Gamma"] = torch.empty_like(dB)
+        if "P" in outputs:
+            d["P_ij"] = torch.empty((nocc, nocc), **kw)
+            d["P_ab"] = torch.empty((nvir, nvir), **kw)
+        if "e_pair" in outputs:
+            d["e_pair"] = torch.empty((nocc, nocc), **kw)
+        frags.append(d)
+    return frags, refs
+
+
+def check(frags, refs):
+    for d, ref in zip(frags, refs):
+        assert energy_error(d["E"], ref["E_hi"], ref["E_lo"]) <= 1e-12 * abs(ref["E_hi"]) + 1e-15
+        for key in ("Gamma", "P_ij", "P_ab", "e_pair"):
+            if key in d:
+                assert rel_fro(d[key].cpu().numpy(), ref[key]) <= 1e-13, key
+
+
+MBE_LIKE = [(5, 25, 90), (12, 60, 216), (7, 35, 126), (3, 15, 54), (9, 45, 162), (6, 30, 108), (2, 10, 36)]
+
+
+def test_grouped_waves_and_solo_match_oracle():
+    frags, refs = make_frags(MBE_LIKE)
+    # a small wave budget: the largest fragments run alone, the rest in several waves
+    opts = rm.make_opts(slab_budget_bytes=3 << 20)
+    status = torch.full((len(frags),), 7, dtype=torch.int32, device="cuda:0")
+    say("batch of %d fragments, small wave budget" % len(frags))
+    rm.fragment_batch(frags, status=status, opts=opts)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(frags)
+    check(frags, refs)
+
+
+def test_batch_output_subsets():
+    frags, refs = make_frags(MBE_LIKE[:4], outputs=("e_pair",))
+    say("energy-only batch")
+    rm.fragment_batch(frags)
+    torch.cuda.synchronize()
+    check(frags, refs)
+
+
+def test_batch_gap_status_per_fragment():
+    frags, refs = make_frags(MBE_LIKE[:3])
+    bad = frags[1]
+    ev = bad["eps_vir"].clone()
+    ev[0] = bad["eps_occ"].max() - 1e-3
+    bad["eps_vir"] = ev
+    status = torch.full((3,), 7, dtype=torch.int32, device="cuda:0")
+    rm.fragment_batch(frags, status=status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0, rm.RIMP2_EGAP, 0]
+    check([frags[0], frags[2]], [refs[0], refs[2]])
+
+
+def test_batch_graph_capture_replays():
+    frags, refs = make_frags(MBE_LIKE[:5])
+    b = rm.Batch(frags)
+    ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    status = torch.zeros(len(frags), dtype=torch.int32, device="cuda:0")
+    b.run(ws, status)
+    torch.cuda.synchronize()
+    check(frags, refs)
+    eager = [{k: v.clone() for k, v in d.items() if k not in ("B", "eps_occ", "eps_vir")} for d in frags]
+    # capture (warm-up on the side stream first, as torch recommends)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(ws, status)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run(ws, status)
+    for rep in range(3):
+        for d in frags:   # scribble over the outputs with eager work between replays
+            for k, v in d.items():
+                if k not in ("B", "eps_occ", "eps_vir"):
+                    v.fill_(float("nan") if v.dtype == torch.float64 else 0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("graph replay %d" % rep)
+        for d, e in zip(frags, eager):
+            for k, v in e.items():
+                assert torch.equal(d[k], v), (rep, k)
+    b.close()
