@@ -56,7 +56,25 @@ struct GemmParams {
   int64_t ldc;
   int64_t split_stride;
   const int32_t* status;  // nonzero: do nothing
+  // Optional pair screening of an (ia|jb) slab: row m belongs to occupied
+  // orbital skip_k0 + m / skip_nvir, column n to skip_j0 + n / skip_nvir; a
+  // tile whose pairs are all marked in skip[k * skip_nocc + j] is not computed.
+  const uint8_t* skip;
+  int32_t skip_nvir, skip_k0, skip_j0, skip_nocc;
 };
+
+// True when every occupied pair a tile touches is screened out (uniform).
+template <int BM, int BN>
+__device__ __forceinline__ bool tile_screened(const GemmParams& p, int tm, int tn) {
+  if (p.skip == nullptr) return false;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t k_lo = m0 / p.skip_nvir, k_hi = (min(p.M, m0 + BM) - 1) / p.skip_nvir;
+  const int64_t j_lo = n0 / p.skip_nvir, j_hi = (min(p.N, n0 + BN) - 1) / p.skip_nvir;
+  for (int64_t k = k_lo; k <= k_hi; ++k)
+    for (int64_t j = j_lo; j <= j_hi; ++j)
+      if (p.skip[(p.skip_k0 + k) * p.skip_nocc + p.skip_j0 + j] == 0) return false;
+  return true;
+}
 
 // Maps the hardware workgroup id to a logical id so that the workgroups one
 // XCD runs (dispatch is round-robin over the 8 XCDs) get consecutive logical
@@ -273,6 +291,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
   const int z = wl / ntiles;
   int tm, tn;
   decode_tile<TRI>(p, wl - z * ntiles, tm, tn);
+  if (tile_screened<BM, BN>(p, tm, tn)) return;
   gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI>(p, tm, tn, z, lds);
 }
 

@@ -84,8 +84,12 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
 }
 
 // Amplitude pass over one slab group.
-// V/X slab: element (kk, a, j, b) at S[((kk*nvir + a)*nocc + j)*nvir + b], kk < g.
-// One workgroup per occupied pair (k = k0 + kk, j).  For each pair of 32x32
+// V/X slab: element (kk, a, jj, b) at S[((kk*nvir + a)*ncols + jj)*nvir + b],
+// kk < g, jj < ncols, occupied pair (k, j) = (k0 + kk, j0 + jj).
+// One workgroup per pair.  With sym (energy only, slab holding j >= k0 only),
+// pairs with j < k are left to their mirror and e_kj is written to both e_kj
+// and e_jk (e_ij = e_ji).  A screened pair (pair_skip) writes e = 0 (and, unless
+// energy_only, zero X and T) without reading V.  For each pair of 32x32
 // tiles (ta <= tb) of the nvir x nvir block it reads V at (a,b) and (b,a),
 // forms X = V / D with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b in that
 // order (so X^T uses D[b,a] rounded its own way), then T = 2X - X^T, writes
@@ -94,14 +98,22 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
 // reduction order.  pair_skip (may be null) zeroes skipped pairs.
 constexpr int AT = 32;
 __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
-                                                int nvir, int k0, int energy_only, const uint8_t* pair_skip,
-                                                double* e_pair, int kk, int j) {
+                                                int nvir, int k0, int j0, int ncols, int sym, int energy_only,
+                                                const uint8_t* pair_skip, double* e_pair, int kk, int jj) {
   __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];
-  const int k = k0 + kk;
-  const int64_t ld = (int64_t)nocc * nvir;
-  double* blk = S + ((int64_t)kk * nvir * nocc + j) * nvir;  // element (a,b) at blk[a*ld + b]
-  double* tblk = Tslab + ((int64_t)kk * nvir * nocc + j) * nvir;
+  const int k = k0 + kk, j = j0 + jj;
+  if (sym && j < k) return;
+  const int64_t ld = (int64_t)ncols * nvir;
+  double* blk = S + ((int64_t)kk * nvir * ncols + jj) * nvir;  // element (a,b) at blk[a*ld + b]
+  double* tblk = Tslab + ((int64_t)kk * nvir * ncols + jj) * nvir;
   const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
+  if (skip && energy_only) {
+    if (threadIdx.x == 0) {
+      e_pair[(int64_t)k * nocc + j] = 0.0;
+      if (sym) e_pair[(int64_t)j * nocc + k] = 0.0;
+    }
+    return;
+  }
   const double ekj = eo[k] + eo[j];
   const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;  // 8 rows x 32 cols per pass
   const int nt = (nvir + AT - 1) / AT;
@@ -161,16 +173,19 @@ __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const 
   double h, l;
   fast_two_sum(sh, sl, h, l);
   block_dd_reduce(h, l);
-  if (t == 0) e_pair[(int64_t)k * nocc + j] = h + l;
+  if (t == 0) {
+    e_pair[(int64_t)k * nocc + j] = h + l;
+    if (sym) e_pair[(int64_t)j * nocc + k] = h + l;
+  }
 }
 
 __global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
-                                                        int nocc, int nvir, int k0, int energy_only,
-                                                        const uint8_t* pair_skip, double* e_pair,
+                                                        int nocc, int nvir, int k0, int j0, int ncols, int sym,
+                                                        int energy_only, const uint8_t* pair_skip, double* e_pair,
                                                         const int32_t* status) {
   if (*status != 0) return;
-  const int kk = blockIdx.x / nocc, j = blockIdx.x - kk * nocc;
-  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, energy_only, pair_skip, e_pair, kk, j);
+  const int kk = blockIdx.x / ncols, jj = blockIdx.x - kk * ncols;
+  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, j0, ncols, sym, energy_only, pair_skip, e_pair, kk, jj);
 }
 
 // out[m*ldo + n] = (accumulate ? out : 0) + alpha * sum_{z < splits} W[z*zs + m*ldw + n],

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/rimp2.h"
+#include "common.hpp"
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
 #include "split_int8.hpp"
@@ -31,22 +32,6 @@ using namespace rimp2;
 
 namespace {
 
-thread_local char g_err[512] = "";
-
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char* fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof g_err, fmt, ap);
-  va_end(ap);
-  return code;
-}
-
-#define HIP_TRY(call)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return fail(RIMP2_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
 
 // ---- kernel timing -------------------------------------------------------
 enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
@@ -329,18 +314,26 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
   for (int64_t k0 = 0; k0 < nocc; k0 += P.g) {
     const int64_t gc = std::min<int64_t>(P.g, nocc - k0);
     const double g = (double)gc, slab = 8.0 * g * o * v * v;
-    // (ia|jb) slab: rows (kk, a) of B starting at k0, columns (j, b) over all of B
+    // (ia|jb) slab: rows (kk, a) of B starting at k0, columns (j, b) over all of B;
+    // energy only: columns j >= k0 only (pairs j < k come from their mirror)
+    const int64_t j0 = energy_only ? k0 : 0, ncols = nocc - j0, Lc = ncols * nvir;
     {
       GemmParams gp{};
-      gp.M = gc * nvir; gp.N = L; gp.K = naux; gp.kchunk = naux;
+      gp.M = gc * nvir; gp.N = Lc; gp.K = naux; gp.kchunk = naux;
       gp.A = kop(B + k0 * nvir * naux, naux, INT64_MAX, 0);
-      gp.Bk = kop(B, naux, INT64_MAX, 0);
-      gp.C = V; gp.ldc = L; gp.split_stride = 0; gp.status = status;
-      // unordered-pair share of this slab's ordered pairs
-      const double af = 2.0 * g * v * o * v * x * (o + 1.0) / (2.0 * o);
+      gp.Bk = kop(B + j0 * nvir * naux, naux, INT64_MAX, 0);
+      gp.C = V; gp.ldc = Lc; gp.split_stride = 0; gp.status = status;
+      gp.skip = skip; gp.skip_nvir = (int32_t)nvir; gp.skip_k0 = (int32_t)k0; gp.skip_j0 = (int32_t)j0;
+      gp.skip_nocc = (int32_t)nocc;
+      // algorithmic FLOPs: unordered pairs whose first orbital is in the group
+      // (energy only: exactly the pairs (k, j >= k) computed; otherwise the
+      // unordered-pair share of the ordered pairs computed)
+      const double npairs = energy_only ? g * o - (g * (double)k0 + g * (g - 1.0) / 2.0) : g * o * (o + 1.0) / (2.0 * o);
+      const double af = 2.0 * v * v * x * npairs;
       if (P.split) {
-        if ((rc = run_oz8(P.sv, dbv, L * P.kpv, k0 * nvir, exv, dbv, L * P.kpv, exv, gc * nvir, L, P.kpv, V, L,
-                          status, R_INTS8, af, (double)P.sv * (g * v + o * v) * P.kpv + slab, st)))
+        if ((rc = run_oz8(P.sv, dbv, L * P.kpv, k0 * nvir, exv, dbv + j0 * nvir * P.kpv, L * P.kpv, exv + j0 * nvir,
+                          gc * nvir, Lc, P.kpv, V, Lc, status, R_INTS8, af,
+                          (double)P.sv * (g * v + o * v) * P.kpv + slab, st)))
           return rc;
       } else if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS, false>(gp, st, R_INTS, af,
                                                                           8.0 * (g + o) * v * x + slab))) {
@@ -348,8 +341,9 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       }
     }
     if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
-           hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * nocc)), dim3(256), 0, st, V, T, eo, ev,
-                              (int)nocc, (int)nvir, (int)k0, energy_only ? 1 : 0, skip, ep, status);
+           hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols)), dim3(256), 0, st, V, T, eo, ev,
+                              (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, energy_only ? 1 : 0,
+                              energy_only ? 1 : 0, skip, ep, status);
          })))
       return rc;
     if (P.gamma) {
