@@ -74,10 +74,16 @@ def cpu_baseline(B, eo, ev, nocc, alg_total, sample_slabs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "mbe3"], default="large",
-                    help="large: one fragment 200/1800/6000; mbe3: a batch of MBE3 fragments")
+    ap.add_argument("--workload", choices=["large", "mbe3", "screen"], default="large",
+                    help="large: one fragment 200/1800/6000; mbe3: a batch of MBE3 fragments; "
+                         "screen: learned pair screening on spatially decaying systems")
+    ap.add_argument("--screen-train", type=int, default=200, help="screen: training systems (seeds 4000..)")
+    ap.add_argument("--screen-pairs", type=int, default=128, help="screen: sampled pairs per training system")
+    ap.add_argument("--screen-size", type=str, default="400,2400,7200", help="screen: nocc,nvir,naux")
     ap.add_argument("--mbe3-stride", type=int, default=32,
                     help="mbe3: take every n-th of the 4096 recipe fragments")
+    ap.add_argument("--mbe3-kinds", type=str, default="1,2,3",
+                    help="mbe3: polymer orders to keep (1 monomers, 2 dimers, 3 trimers)")
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nocc", type=int, default=200)
@@ -111,6 +117,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "mbe3":
         return bench_mbe3(args, torch, synth, rm, dev)
+    if args.workload == "screen":
+        return bench_screen(args, torch, synth, rm, dev)
     f = synth.Fragment(args.nocc, args.nvir, args.naux, seed=args.seed, decay=args.decay)
     nocc, nvir, naux = f.nocc, f.nvir, f.naux
     large = (nocc, nvir, naux, args.seed, args.decay) == (200, 1800, 6000, 1001, 1200.0)
@@ -247,7 +255,8 @@ def bench_mbe3(args, torch, synth, rm, dev):
     same batch replayed from a captured graph, and one rimp2_fragment call per
     fragment; value = algorithmic TFLOP/s of the grouped batch."""
     sizes = synth.mbe3_sizes(4096)
-    ids = list(range(0, 4096, args.mbe3_stride))
+    keep = {int(k) for k in args.mbe3_kinds.split(",")}
+    ids = [f for f in range(0, 4096, args.mbe3_stride) if sizes[f][0] in keep]
     frags, total_alg, kinds = [], 0.0, {1: 0, 2: 0, 3: 0}
     print("[bench] generating %d fragments on the GPU" % len(ids), file=sys.stderr, flush=True)
     f64 = dict(dtype=torch.float64, device=dev)
@@ -301,16 +310,30 @@ def bench_mbe3(args, torch, synth, rm, dev):
     order = sorted(range(len(frags)), key=lambda i: -frags[i]["B"].numel() * frags[i]["B"].shape[0])
     ws1 = torch.empty(max(rm.workspace_size(*frags[i]["B"].shape) for i in order), dtype=torch.uint8, device=dev)
 
-    def loop():
+    def loop(opts=None):
         for i in order:
             d = frags[i]
             rm.fragment_into(d["B"], d["eps_occ"], d["eps_vir"], d["E"], d["Gamma"], d["P_ij"], d["P_ab"],
-                             d["e_pair"], workspace=ws1)
+                             d["e_pair"], workspace=ws1, opts=opts)
     loop()
     t_loop = timed(loop, args.steps)
     print("[bench] per-fragment loop %.3f s" % t_loop, file=sys.stderr, flush=True)
-    E_loop = torch.stack([d["E"] for d in frags])
+    E_loop = torch.stack([d["E"] for d in frags]).clone()
     dE = float((E_loop - E_batch).abs().max())
+    # in-situ tile autotuning: the first pass trials the candidates, later passes use the choices
+    rm.autotune_reset()
+    tuned = rm.make_opts(autotune=True)
+    t_trial = timed(lambda: loop(tuned), 1)
+    loop(tuned)
+    torch.cuda.synchronize()
+    t_tuned = timed(lambda: loop(tuned), args.steps)
+    rep = rm.autotune_report()
+    E_tuned = torch.stack([d["E"] for d in frags])
+    tuned_bitwise = bool(torch.equal(E_tuned, E_loop))
+    n_changed = sum(1 for e in rep if e["best"] > 0)
+    print("[bench] per-fragment loop, autotuned: trial pass %.3f s, tuned %.3f s; %d of %d shapes off the default"
+          % (t_trial, t_tuned, n_changed, len(rep)), file=sys.stderr, flush=True)
+    rm.autotune_reset()
     if args.stats:
         for st in sorted(stats, key=lambda x: -x["total_ms"]):
             print("[bench] %-14s launches=%5d total=%10.2f ms" % (st["name"], st["launches"], st["total_ms"]),
@@ -322,18 +345,155 @@ def bench_mbe3(args, torch, synth, rm, dev):
         "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "mbe3 batch: %d of the 4096 recipe fragments (every %d-th): %d monomers, %d dimers, "
-                               "%d trimers" % (len(ids), args.mbe3_stride, kinds[1], kinds[2], kinds[3]),
+        "config": {"workload": "mbe3 batch: %d of the 4096 recipe fragments (every %d-th, orders %s): %d monomers, "
+                               "%d dimers, %d trimers" % (len(ids), args.mbe3_stride, args.mbe3_kinds, kinds[1],
+                                                          kinds[2], kinds[3]),
                    "fragments": len(ids), "flops_counted": "algorithmic E+Gamma+P_ab+P_ij"},
         "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4),
         "graph_replay_tflops": round(total_alg / t_graph / 1e12, 4),
         "per_fragment_loop_tflops": round(total_alg / t_loop / 1e12, 4),
         "speedup_batch_vs_loop": round(t_loop / t_batch, 4),
         "speedup_graph_vs_loop": round(t_loop / t_graph, 4),
+        "autotune": {"loop_tuned_tflops": round(total_alg / t_tuned / 1e12, 4),
+                     "loop_trial_pass_tflops": round(total_alg / t_trial / 1e12, 4),
+                     "speedup_tuned_vs_fixed_loop": round(t_loop / t_tuned, 4),
+                     "shapes": len(rep), "shapes_off_default": n_changed, "E_bitwise_equal_to_fixed": tuned_bitwise},
         "max_abs_dE_batch_vs_loop_Eh": dE,
         "roofline": {"bound": "mfma", "kernel": dom["name"] + " (grouped)", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None,
                      "note": "grouped launches mix fragments; per-launch algorithmic FLOPs are not split by role"},
+    }
+    print(json.dumps(out))
+
+
+def bench_screen(args, torch, synth, rm, dev):
+    """Learned pair screening.  Training: for each system (seeds 4000..), the
+    energy-only kernel runs on distance-stratified sampled pairs (all others
+    skipped) and its e_ij become log10|e_ij| targets for the 4-64-64-1 network,
+    trained with the library's kernels.  Evaluation (held-out seed 4200): an
+    unscreened energy-only run judges the screens; value = algorithmic TFLOP/s
+    of the full energy (nocc(nocc+1) nvir^2 naux) over the screened run's time,
+    with the threshold chosen so the predicted skipped energy is <= 0.5 uEh."""
+    import math
+    from paper_2410_21888_amd import screen as SC
+    nocc, nvir, naux = (int(v) for v in args.screen_size.split(","))
+    f64 = dict(dtype=torch.float64, device=dev)
+    B = torch.empty((nocc, nvir, naux), **f64)
+    e_pair = torch.empty((nocc, nocc), **f64)
+    E = torch.zeros(2, **f64)
+    ws = torch.empty(rm.workspace_size(nocc, nvir, naux, False, False), dtype=torch.uint8, device=dev)
+
+    def load(seed):
+        F = synth.screen_system(seed, nocc, nvir, naux)
+        F.B_device(B)
+        eo, ev = F.eps()
+        r, _ = F.positions()
+        return (torch.from_numpy(eo).to(dev), torch.from_numpy(ev).to(dev), torch.from_numpy(r).to(dev), r)
+
+    def run(eo, ev, skip=None):
+        opts = rm.make_opts(pair_skip=skip)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rm.fragment_into(B, eo, ev, E, e_pair=e_pair, workspace=ws, opts=opts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    iu = np.triu_indices(nocc, 1)
+    xs, ts = [], []
+    t_data = time.perf_counter()
+    for n in range(args.screen_train):
+        seed = 4000 + n
+        eo, ev, r_dev, r = load(seed)
+        feat, _ = SC.pair_features(B, eo, ev, r_dev, bound=False)
+        # sample pairs i < j uniformly over distance bins
+        d = np.sqrt(((r[iu[0]] - r[iu[1]]) ** 2).sum(-1))
+        rng = np.random.default_rng(seed)
+        bins = np.minimum((d / d.max() * 16).astype(int), 15)
+        w = 1.0 / np.bincount(bins, minlength=16)[bins]
+        pick = rng.choice(len(d), size=min(args.screen_pairs, len(d)), replace=False, p=w / w.sum())
+        pi, pj = iu[0][pick], iu[1][pick]
+        mask = np.ones((nocc, nocc), dtype=np.uint8)
+        mask[pi, pj] = 0
+        mask[pj, pi] = 0
+        run(eo, ev, torch.from_numpy(mask).to(dev))
+        flat = torch.from_numpy(pi * nocc + pj).to(dev)
+        ts.append(SC.log_energy(e_pair.reshape(-1).index_select(0, flat).contiguous()))
+        xs.append(feat.index_select(0, flat))
+        if n % 20 == 0:
+            print("[bench] training system %d/%d" % (n + 1, args.screen_train), file=sys.stderr, flush=True)
+    t_data = time.perf_counter() - t_data
+    X = torch.cat(xs).contiguous()
+    T = torch.cat(ts).contiguous()
+    params = SC.init_params(0, dev)
+    tr = SC.Trainer(params, lr=2e-3)
+    t_fit = time.perf_counter()
+    loss = tr.fit(X, T, steps=3000, batch=4096, seed=1)
+    tr.lr = 3e-4
+    loss = tr.fit(X, T, steps=2000, batch=4096, seed=2)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t_fit
+    print("[bench] trained on %d pairs: final minibatch loss %.4f (log10 units^2)" % (len(T), loss),
+          file=sys.stderr, flush=True)
+
+    # evaluation system
+    eo, ev, r_dev, r = load(4200)
+    feat, bound = SC.pair_features(B, eo, ev, r_dev, bound=True)
+    pred = SC.mlp_forward(feat, tr.params)
+    t0 = run(eo, ev)
+    print("[bench] unscreened energy-only run %.3f s" % t0, file=sys.stderr, flush=True)
+    ep0 = e_pair.cpu().numpy().copy()
+    E0 = E.cpu().numpy().copy()
+    off = ~np.eye(nocc, dtype=bool)
+    ptrue = np.log10(np.maximum(-ep0[iu], 1e-300))
+    pp = pred.reshape(nocc, nocc).cpu().numpy()[iu]
+    rmse = float(np.sqrt(np.mean((pp - ptrue) ** 2)))
+
+    def exact_error(mask):
+        return abs(math.fsum(ep0[mask > 0].tolist()))
+
+    # literal threshold (1e-7 Eh) and the budgeted threshold
+    lit, lit_e = SC.screen_mask(pred, nocc, -7.0)
+    lo, hi = -20.0, 0.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        _, se = SC.screen_mask(pred, nocc, mid)
+        lo, hi = (mid, hi) if float(se) <= 0.5e-6 else (lo, mid)
+    bud, bud_e = SC.screen_mask(pred, nocc, lo)
+    t1 = run(eo, ev, bud)
+    E1 = E.cpu().numpy().copy()
+    dE_run = abs(math.fsum([float(E1[0]), float(E1[1]), -float(E0[0]), -float(E0[1])]))
+    print("[bench] screened run %.3f s" % t1, file=sys.stderr, flush=True)
+    # rigorous bound screen with the same budget: skip the smallest bounds while their sum <= 1 uEh
+    bd = bound.cpu().numpy()
+    order = np.argsort(bd[iu])
+    csum = np.cumsum(2 * bd[iu][order])
+    nb = int(np.searchsorted(csum, 1e-6, side="right"))
+    bmask = np.zeros((nocc, nocc), dtype=np.uint8)
+    bmask[iu[0][order[:nb]], iu[1][order[:nb]]] = 1
+    bmask |= bmask.T
+    npairs = nocc * (nocc - 1)
+    lit_np, bud_np = lit.cpu().numpy(), bud.cpu().numpy()
+    alg = float(nocc) * (nocc + 1) * nvir * nvir * naux
+    value = alg / t1 / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(t1 * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "learned pair screening: energy-only, nocc=%d nvir=%d naux=%d, 40 A cube, 3 A decay"
+                               % (nocc, nvir, naux), "train_systems": args.screen_train,
+                   "train_pairs": int(len(T)), "eval_seed": 4200,
+                   "flops_counted": "algorithmic full energy nocc(nocc+1) nvir^2 naux"},
+        "unscreened_s": round(t0, 3), "screened_s": round(t1, 3), "speedup_screened_vs_unscreened": round(t0 / t1, 4),
+        "screen_budgeted": {"threshold_log10": lo, "skipped_pair_fraction": float(bud_np[off].mean()),
+                            "predicted_skipped_Eh": float(bud_e), "exact_skipped_Eh": exact_error(bud_np),
+                            "abs_dE_run_Eh": dE_run},
+        "screen_literal_1e-7": {"skipped_pair_fraction": float(lit_np[off].mean()),
+                                "predicted_skipped_Eh": float(lit_e), "exact_skipped_Eh": exact_error(lit_np)},
+        "bound_screen_1uEh": {"skipped_pair_fraction": nb * 2 / npairs, "exact_skipped_Eh": exact_error(bmask)},
+        "model": {"rmse_log10_eval": rmse, "train_data_s": round(t_data, 1), "train_fit_s": round(t_fit, 1)},
+        "E_unscreened": [float(E0[0]), float(E0[1])],
+        "roofline": {"bound": "mfma", "kernel": "ints_gemm", "achieved": None, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": None, "traffic": None},
     }
     print(json.dumps(out))
 

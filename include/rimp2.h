@@ -82,6 +82,9 @@ typedef struct {
   const uint8_t* pair_skip; /* device [nocc][nocc] or NULL: nonzero (i,j) marks
                                an occupied pair whose (ia|jb) block is skipped
                                (screening); must be symmetric */
+  int32_t autotune;         /* nonzero: choose each FP64 GEMM's tile shape in situ
+                               (rimp2_autotune_report); 0 = fixed shapes */
+  int32_t reserved;
 } rimp2_opts;
 
 /* Library version, major*10000 + minor*100 + patch. */
@@ -215,6 +218,42 @@ typedef struct {
 int rimp2_timing_enable(int enable);
 /* Writes up to `capacity` entries to `stats` and their number to *count. */
 int rimp2_timing_collect(rimp2_kernel_stat* stats, int32_t capacity, int32_t* count);
+
+/*
+ * In-situ GEMM autotuning (Sec. "GEMM runtime auto-tuning": each variant of a
+ * GEMM shape is timed with HIP events on real calls, then the fastest is used
+ * for every later call of that shape).  Here the variants are the output tile
+ * shapes of the FP64 MFMA GEMMs of rimp2_fragment (and of the fragments a
+ * batch runs alone), not transposed operand layouts: the slab layout already
+ * fixes the operands.  A shape is (role, M, N, K, split length, 16-byte-load
+ * eligibility) on one device.  With opts->autotune set, the first launches of
+ * a shape run each candidate twice, bracketed by events on the launch's
+ * stream; the host never waits for them, and once every candidate's events
+ * have completed (checked without blocking at the next launch of the shape),
+ * the candidate with the smallest time is used from then on.  Until then
+ * launches use the fixed default.  Nothing is trialled while the stream is
+ * being captured into a graph.  The tile shape does not change the order in
+ * which any output element is summed, so results are bitwise identical
+ * whichever candidate runs.  The table is process-wide and thread-safe.
+ */
+typedef struct {
+  char    role[32];      /* "ints_gemm", "gamma_gemm", "pab_gemm", "pij_gemm" */
+  int32_t device;
+  int32_t nvar;          /* candidates */
+  int32_t best;          /* chosen candidate, -1 while trials are pending */
+  int32_t vec;           /* 16-byte loads eligible */
+  int64_t M, N, K, kchunk;
+  int32_t tile_m[4], tile_n[4];   /* candidate tile shapes, [0] = default */
+  int32_t timed[4];      /* completed trials per candidate */
+  double  min_ms[4];     /* fastest completed trial per candidate */
+  int64_t uses;          /* launches of this shape so far */
+} rimp2_tune_stat;
+
+/* Writes up to `capacity` entries to `stats` and the number written to *count
+   (polls pending trials first, without blocking). */
+int rimp2_autotune_report(rimp2_tune_stat* stats, int32_t capacity, int32_t* count);
+/* Forgets every shape and decision. */
+int rimp2_autotune_reset(void);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rimp2.h"
@@ -121,6 +123,7 @@ struct Plan {
   int64_t nocc, nvir, naux;
   bool gamma, density;
   bool split;                // RIMP2_SPLIT_INT8
+  bool autotune;             // in-situ tile choice of the FP64 GEMMs
   int sv, sg;                // digits per operand of (ia|jb) and of Gamma
   int64_t kpv, kpg;          // padded reduction lengths of the split products
   size_t off_dbv, off_ev, off_dbg, off_eg, off_cmax, off_dt, off_et;
@@ -139,6 +142,7 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
     return fail(RIMP2_ENOTSUP, "precision %d is not supported", o->precision);
   p->nocc = nocc; p->nvir = nvir; p->naux = naux; p->gamma = gamma; p->density = density;
   p->split = o && o->precision == RIMP2_SPLIT_INT8;
+  p->autotune = o && o->autotune != 0;
   p->sv = (o && o->split_slices) ? o->split_slices : 7;
   p->sg = (o && o->split_slices_gamma) ? o->split_slices_gamma : 5;
   if (p->split && (p->sv < 3 || p->sv > 7 || p->sg < 3 || p->sg > 7))
@@ -193,6 +197,11 @@ bool kop_vec(const KOperand& o, int64_t K) {
   return (uintptr_t)o.base % 16 == 0 && o.rs % 2 == 0 && (plain || (o.kdiv % 2 == 0 && o.ks1 % 2 == 0));
 }
 
+// 16-byte loads for a whole GEMM (the split length is a multiple of kBK, so even).
+bool gemm_vec(const GemmParams& gp, bool nc) {
+  return kop_vec(gp.A, gp.K) && (nc ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
+}
+
 template <int BM, int BN, bool NC, int ROLE, bool TRI>
 int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   gp.tiles_m = (int32_t)cdiv(gp.M, BM);
@@ -205,8 +214,7 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   const int64_t tiles = TRI ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
   const int64_t nwg = tiles * gp.splits;
   if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "GEMM grid too large (%lld workgroups)", (long long)nwg);
-  const bool vec = kop_vec(gp.A, gp.K) && gp.kchunk % 2 == 0 &&
-                   (NC ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
+  const bool vec = gemm_vec(gp, NC);
   const double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
   return traced(role, af, ef, ab, st, [&] {
     if (vec)
@@ -214,6 +222,189 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
     else
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, false, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
   });
+}
+
+
+// ---- in-situ tile autotuner (Sec. "GEMM runtime auto-tuning") -------------
+// Candidates are output tile shapes; the split length (and with it every
+// element's summation order) comes from the plan and is the same for all.
+struct TileShape {
+  int bm, bn;
+};
+constexpr int kTuneVars = 4, kTuneTrials = 2;
+
+// Candidate tile shapes of a role's GEMM, the fixed default first.
+int tile_candidates(int role, const GemmParams& gp, TileShape* c) {
+  switch (role) {
+    case R_INTS:
+    case R_GAMMA:
+      c[0] = {128, 128}; c[1] = {64, 64};
+      return 2;
+    case R_PAB: {
+      const bool t96 = pab_tile96(gp.M);
+      c[0] = t96 ? TileShape{96, 96} : TileShape{128, 128};
+      c[1] = t96 ? TileShape{128, 128} : TileShape{96, 96};
+      c[2] = {64, 64};
+      return 3;
+    }
+    case R_PIJ:
+      c[0] = {64, 64}; c[1] = {128, 128}; c[2] = {32, 32};
+      return 3;
+    default:
+      return 0;
+  }
+}
+
+// The GEMM of `role` with square tiles of side bm (one of its candidates).
+int launch_role(int role, int bm, const GemmParams& gp, hipStream_t st, double af, double ab) {
+  switch (role) {
+    case R_INTS:
+      return bm == 64 ? launch_gemm<64, 64, false, ROLE_INTS, false>(gp, st, role, af, ab)
+                      : launch_gemm<128, 128, false, ROLE_INTS, false>(gp, st, role, af, ab);
+    case R_GAMMA:
+      return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA, false>(gp, st, role, af, ab)
+                      : launch_gemm<128, 128, true, ROLE_GAMMA, false>(gp, st, role, af, ab);
+    case R_PAB:
+      return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, false>(gp, st, role, af, ab)
+             : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, false>(gp, st, role, af, ab)
+                        : launch_gemm<128, 128, false, ROLE_PAB, false>(gp, st, role, af, ab);
+    case R_PIJ:
+      return bm == 32    ? launch_gemm<32, 32, false, ROLE_PIJ, true>(gp, st, role, af, ab)
+             : bm == 128 ? launch_gemm<128, 128, false, ROLE_PIJ, true>(gp, st, role, af, ab)
+                         : launch_gemm<64, 64, false, ROLE_PIJ, true>(gp, st, role, af, ab);
+    default:
+      return fail(RIMP2_EINVAL, "no GEMM for role %d", role);
+  }
+}
+
+struct TuneKey {
+  int dev, role, vec;
+  int64_t M, N, K, kchunk;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, role, vec, M, N, K, kchunk) < std::tie(o.dev, o.role, o.vec, o.M, o.N, o.K, o.kchunk);
+  }
+};
+struct TunePending {
+  int var;
+  hipEvent_t e0, e1;
+};
+struct TuneEntry {
+  int nvar = 0, best = -1;
+  TileShape cand[kTuneVars] = {};
+  int launched[kTuneVars] = {}, timed[kTuneVars] = {};
+  double min_ms[kTuneVars] = {};
+  int64_t uses = 0;
+  std::vector<TunePending> pend;
+};
+struct Tuner {
+  std::mutex mu;
+  std::map<TuneKey, TuneEntry> tab;
+  std::vector<hipEvent_t> pool;
+};
+Tuner& tuner() {
+  static Tuner t;
+  return t;
+}
+
+// Folds the completed trials of e into its timings without blocking, and
+// decides once every candidate has kTuneTrials of them: the fastest (by its
+// fastest trial), unless it beats the default by less than 2%.  Caller holds
+// the tuner lock.
+void tune_poll(Tuner& U, TuneEntry& e) {
+  for (size_t i = 0; i < e.pend.size();) {
+    const TunePending q = e.pend[i];
+    const hipError_t r = hipEventQuery(q.e1);
+    if (r == hipErrorNotReady) {
+      (void)hipGetLastError();
+      ++i;
+      continue;
+    }
+    float ms = 0.f;
+    if (r == hipSuccess && hipEventElapsedTime(&ms, q.e0, q.e1) == hipSuccess) {
+      e.min_ms[q.var] = e.timed[q.var] ? std::min(e.min_ms[q.var], (double)ms) : (double)ms;
+      e.timed[q.var] += 1;
+    } else {
+      (void)hipGetLastError();
+      e.launched[q.var] -= 1;  // trial lost: it is run again
+    }
+    U.pool.push_back(q.e0);
+    U.pool.push_back(q.e1);
+    e.pend[i] = e.pend.back();
+    e.pend.pop_back();
+  }
+  if (e.best >= 0) return;
+  int best = 0;
+  for (int v = 0; v < e.nvar; ++v) {
+    if (e.timed[v] < kTuneTrials) return;
+    if (e.min_ms[v] < e.min_ms[best] && e.min_ms[v] < 0.98 * e.min_ms[0]) best = v;
+  }
+  e.best = best;
+}
+
+// Launches the GEMM of `role`: the default tile shape, or with autotuning the
+// shape's chosen candidate (a candidate still owed a trial, bracketed by
+// events, while the choice is open and the stream is not capturing).
+int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, double af, double ab) {
+  TileShape c[kTuneVars];
+  const int nvar = tile_candidates(role, gp, c);
+  if (!autotune || nvar < 2) return launch_role(role, c[0].bm, gp, st, af, ab);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    cs = hipStreamCaptureStatusActive;
+  }
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const TuneKey key{dev, role, gemm_vec(gp, role == R_GAMMA) ? 1 : 0, gp.M, gp.N, gp.K, gp.kchunk};
+  Tuner& U = tuner();
+  int v = 0;
+  bool trial = false;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  {
+    std::lock_guard<std::mutex> lk(U.mu);
+    TuneEntry& e = U.tab[key];
+    if (e.nvar == 0) {
+      e.nvar = nvar;
+      for (int i = 0; i < nvar; ++i) e.cand[i] = c[i];
+    }
+    e.uses += 1;
+    if (!capturing) tune_poll(U, e);
+    if (e.best >= 0) {
+      v = e.best;
+    } else if (!capturing) {
+      for (int i = 0; i < nvar && !trial; ++i)
+        if (e.launched[i] < kTuneTrials) { v = i; trial = true; }
+    }
+    for (int i = 0; trial && i < 2; ++i) {
+      if (!U.pool.empty()) {
+        ev[i] = U.pool.back();
+        U.pool.pop_back();
+      } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        if (i == 1) U.pool.push_back(ev[0]);
+        trial = false;
+        v = 0;
+      }
+    }
+    if (trial) e.launched[v] += 1;
+  }
+  const bool rec0 = trial && hipEventRecord(ev[0], st) == hipSuccess;
+  const int rc = launch_role(role, c[v].bm, gp, st, af, ab);
+  if (trial) {
+    const bool ok = rec0 && rc == RIMP2_OK && hipEventRecord(ev[1], st) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(U.mu);
+    TuneEntry& e = U.tab[key];
+    if (ok) {
+      e.pend.push_back(TunePending{v, ev[0], ev[1]});
+    } else {
+      e.launched[v] -= 1;
+      U.pool.push_back(ev[0]);
+      U.pool.push_back(ev[1]);
+    }
+  }
+  return rc;
 }
 
 
@@ -335,8 +526,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
                           gc * nvir, Lc, P.kpv, V, Lc, status, R_INTS8, af,
                           (double)P.sv * (g * v + o * v) * P.kpv + slab, st)))
           return rc;
-      } else if ((rc = launch_gemm<kTile, kTile, false, ROLE_INTS, false>(gp, st, R_INTS, af,
-                                                                          8.0 * (g + o) * v * x + slab))) {
+      } else if ((rc = launch_tuned(R_INTS, gp, P.autotune, st, af, 8.0 * (g + o) * v * x + slab))) {
         return rc;
       }
     }
@@ -365,7 +555,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       } else if (P.s_gam > 1) {
         double* W = (double*)(ws + P.off_gam);
         gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux; gp.status = status;
-        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA, false>(gp, st, R_GAMMA, af, ab))) return rc;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, st, af, ab))) return rc;
         const int64_t splits = cdiv(L, cdiv(cdiv(L, P.s_gam), kBK) * kBK);
         const int64_t n = gc * nvir * naux;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
@@ -375,7 +565,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
           return rc;
       } else {
         gp.C = out; gp.ldc = naux; gp.split_stride = 0; gp.status = status;
-        if ((rc = launch_gemm<kTile, kTile, true, ROLE_GAMMA, false>(gp, st, R_GAMMA, af, ab))) return rc;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, st, af, ab))) return rc;
       }
     }
     if (P.density) {
@@ -390,12 +580,8 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         double* W = (double*)(ws + P.off_pab);
         gp.C = W; gp.ldc = nvir; gp.split_stride = nvir * nvir; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ab), kBK) * kBK);
-        rc = pab_tile96(nvir)
-                 ? launch_gemm<96, 96, false, ROLE_PAB, false>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
-                                                              2.0 * slab + 8.0 * splits * v * v)
-                 : launch_gemm<kTile, kTile, false, ROLE_PAB, false>(gp, st, R_PAB, 2.0 * v * v * g * o * v,
-                                                                    2.0 * slab + 8.0 * splits * v * v);
-        if (rc) return rc;
+        if ((rc = launch_tuned(R_PAB, gp, P.autotune, st, 2.0 * v * v * g * o * v, 2.0 * slab + 8.0 * splits * v * v)))
+          return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * v * v, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nvir * nvir, 256)), dim3(256), 0, st, Pab,
                                   nvir, W, nvir, nvir * nvir, (int)splits, nvir, nvir, 1.0, accumulate, status);
@@ -413,8 +599,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         gp.C = W; gp.ldc = nocc; gp.split_stride = nocc * nocc; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ij), kBK) * kBK);
         // each slab's contribution to P_ij is symmetric: upper-triangular tiles, mirrored
-        if ((rc = launch_gemm<kSmallTile, kSmallTile, false, ROLE_PIJ, true>(gp, st, R_PIJ, 2.0 * o * o * g * v * v,
-                                                                             2.0 * slab + 8.0 * splits * o * o)))
+        if ((rc = launch_tuned(R_PIJ, gp, P.autotune, st, 2.0 * o * o * g * v * v, 2.0 * slab + 8.0 * splits * o * o)))
           return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * o * o, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nocc * nocc, 256)), dim3(256), 0, st, Pij,
@@ -901,6 +1086,47 @@ int rimp2_timing_collect(rimp2_kernel_stat* stats, int32_t capacity, int32_t* co
       ++n;
     }
   *count = std::min(n, capacity);
+  return RIMP2_OK;
+}
+
+int rimp2_autotune_report(rimp2_tune_stat* stats, int32_t capacity, int32_t* count) {
+  if (!count || (capacity > 0 && !stats)) return fail(RIMP2_EINVAL, "bad autotune_report arguments");
+  Tuner& U = tuner();
+  std::lock_guard<std::mutex> lk(U.mu);
+  int32_t n = 0;
+  for (auto& kv : U.tab) {
+    TuneEntry& e = kv.second;
+    tune_poll(U, e);
+    if (n >= capacity) break;
+    rimp2_tune_stat& t = stats[n++];
+    memset(&t, 0, sizeof t);
+    snprintf(t.role, sizeof t.role, "%s", kRoleName[kv.first.role]);
+    t.device = kv.first.dev;
+    t.nvar = e.nvar;
+    t.best = e.best;
+    t.vec = kv.first.vec;
+    t.M = kv.first.M; t.N = kv.first.N; t.K = kv.first.K; t.kchunk = kv.first.kchunk;
+    for (int v = 0; v < e.nvar && v < 4; ++v) {
+      t.tile_m[v] = e.cand[v].bm;
+      t.tile_n[v] = e.cand[v].bn;
+      t.timed[v] = e.timed[v];
+      t.min_ms[v] = e.min_ms[v];
+    }
+    t.uses = e.uses;
+  }
+  *count = n;
+  return RIMP2_OK;
+}
+
+int rimp2_autotune_reset(void) {
+  Tuner& U = tuner();
+  std::lock_guard<std::mutex> lk(U.mu);
+  for (auto& kv : U.tab)
+    for (auto& q : kv.second.pend) {
+      U.pool.push_back(q.e0);
+      U.pool.push_back(q.e1);
+    }
+  U.tab.clear();
   return RIMP2_OK;
 }
 

@@ -35,6 +35,8 @@ class Opts(ctypes.Structure):
         ("split_slices_gamma", ctypes.c_int32),
         ("slab_budget_bytes", ctypes.c_size_t),
         ("pair_skip", ctypes.c_void_p),
+        ("autotune", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -45,6 +47,14 @@ class FragDesc(ctypes.Structure):
         ("E", ctypes.c_void_p), ("Gamma", ctypes.c_void_p), ("P_ij", ctypes.c_void_p),
         ("P_ab", ctypes.c_void_p), ("e_pair", ctypes.c_void_p),
     ]
+
+
+class TuneStat(ctypes.Structure):
+    _fields_ = [("role", ctypes.c_char * 32), ("device", ctypes.c_int32), ("nvar", ctypes.c_int32),
+                ("best", ctypes.c_int32), ("vec", ctypes.c_int32), ("M", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int64), ("kchunk", ctypes.c_int64), ("tile_m", ctypes.c_int32 * 4),
+                ("tile_n", ctypes.c_int32 * 4), ("timed", ctypes.c_int32 * 4), ("min_ms", ctypes.c_double * 4),
+                ("uses", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -89,6 +99,10 @@ def lib():
         L.rimp2_timing_enable.argtypes = [ctypes.c_int]
         L.rimp2_timing_collect.restype = ctypes.c_int
         L.rimp2_timing_collect.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+        L.rimp2_autotune_report.restype = ctypes.c_int
+        L.rimp2_autotune_report.argtypes = [ctypes.POINTER(TuneStat), i32, ctypes.POINTER(i32)]
+        L.rimp2_autotune_reset.restype = ctypes.c_int
+        L.rimp2_autotune_reset.argtypes = []
         _lib = L
     return _lib
 
@@ -109,8 +123,9 @@ def version() -> int:
 
 
 def make_opts(precision: int = FP64, split_slices: int = 0, slab_group: int = 0, slab_budget_bytes: int = 0,
-              pair_skip: Optional[torch.Tensor] = None, split_slices_gamma: int = 0) -> Opts:
+              pair_skip: Optional[torch.Tensor] = None, split_slices_gamma: int = 0, autotune: bool = False) -> Opts:
     o = Opts()
+    o.autotune = 1 if autotune else 0
     o.precision, o.split_slices, o.slab_group = precision, split_slices, slab_group
     o.split_slices_gamma = split_slices_gamma
     o.slab_budget_bytes = slab_budget_bytes
@@ -258,6 +273,25 @@ def timing_collect() -> list:
     _check(lib().rimp2_timing_collect(arr, 32, ctypes.byref(n)))
     return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms, alg_flops=a.alg_flops,
                  exec_flops=a.exec_flops, alg_bytes=a.alg_bytes) for a in arr[:n.value]]
+
+
+def autotune_report() -> list:
+    """Shapes seen by the in-situ tile autotuner, with candidates, trial
+    timings and the decision (best = -1 while trials are pending)."""
+    arr = (TuneStat * 512)()
+    n = ctypes.c_int32(0)
+    _check(lib().rimp2_autotune_report(arr, 512, ctypes.byref(n)))
+    out = []
+    for a in arr[:n.value]:
+        nv = a.nvar
+        out.append(dict(role=a.role.decode(), device=a.device, best=a.best, vec=a.vec, M=a.M, N=a.N, K=a.K,
+                        kchunk=a.kchunk, tiles=[(a.tile_m[v], a.tile_n[v]) for v in range(nv)],
+                        timed=list(a.timed[:nv]), min_ms=list(a.min_ms[:nv]), uses=a.uses))
+    return out
+
+
+def autotune_reset() -> None:
+    _check(lib().rimp2_autotune_reset())
 
 
 class Batch:
