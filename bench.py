@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true",
                     help="after the timed steps run one FP64 step and report the differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="large: in-situ tile autotuning (the warmup steps take the trials)")
     ap.add_argument("--stats", action="store_true", help="print per-kernel statistics to stderr")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device (a plain copy of known size, for "
@@ -138,7 +140,8 @@ def main():
     ep = torch.empty((nocc, nocc), **f64)
     opts = rm.make_opts(slab_group=args.slab_group,
                         precision=rm.SPLIT_INT8 if args.precision == "split" else rm.FP64,
-                        split_slices=args.split_slices, split_slices_gamma=args.split_slices_gamma)
+                        split_slices=args.split_slices, split_slices_gamma=args.split_slices_gamma,
+                        autotune=args.autotune)
     ws = torch.empty(rm.workspace_size(nocc, nvir, naux, True, True, opts), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -201,7 +204,7 @@ def main():
         "config": {"workload": "%s fragment nocc=%d nvir=%d naux=%d" % (workload, nocc, nvir, naux),
                    "nocc": nocc, "nvir": nvir, "naux": naux, "seed": args.seed, "aux_decay": args.decay,
                    "outputs": "E, e_ij, Gamma, P_ij, P_ab", "flops_counted": "algorithmic E+Gamma+P_ab+P_ij",
-                   "slab_group": args.slab_group or "auto"},
+                   "slab_group": args.slab_group or "auto", "autotune": bool(args.autotune)},
         "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4),
         "tflops_executed": round(fl["executed"] / dt / 1e12, 4),
         "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": round(achieved, 4),
@@ -211,6 +214,10 @@ def main():
                      "traffic": traffic},
         "E_hi": float(E[0]), "E_lo": float(E[1]),
     }
+    if args.autotune:
+        out["autotune"] = [dict(role=e["role"], M=e["M"], N=e["N"], K=e["K"], tile=e["tiles"][e["best"]]
+                                if e["best"] >= 0 else None, min_ms=[round(t, 3) for t in e["min_ms"]])
+                           for e in rm.autotune_report()]
     if args.precision == "split":
         out["dtype"] = "int8 digit products (Ozaki), f64 elsewhere"
         out["config"]["precision"] = "split-int8 ints=%d gamma=%d digits" % (args.split_slices or 7,
@@ -320,8 +327,17 @@ def bench_mbe3(args, torch, synth, rm, dev):
     print("[bench] per-fragment loop %.3f s" % t_loop, file=sys.stderr, flush=True)
     E_loop = torch.stack([d["E"] for d in frags]).clone()
     dE = float((E_loop - E_batch).abs().max())
-    # in-situ tile autotuning: the first pass trials the candidates, later passes use the choices
+    # in-situ tile autotuning: the first passes trial the candidates, later passes use the choices
     rm.autotune_reset()
+    tb = rm.Batch(frags, opts=rm.make_opts(autotune=True))
+    for _ in range(5):
+        tb.run(ws, status)
+        torch.cuda.synchronize()
+    t_batch_tuned = timed(lambda: tb.run(ws, status), args.steps)
+    E_bt = torch.stack([d["E"] for d in frags]).clone()
+    batch_tuned_bitwise = bool(torch.equal(E_bt, E_batch))
+    tb.close()
+    print("[bench] grouped batch, autotuned: %.3f s" % t_batch_tuned, file=sys.stderr, flush=True)
     tuned = rm.make_opts(autotune=True)
     t_trial = timed(lambda: loop(tuned), 1)
     loop(tuned)
@@ -331,6 +347,16 @@ def bench_mbe3(args, torch, synth, rm, dev):
     E_tuned = torch.stack([d["E"] for d in frags])
     tuned_bitwise = bool(torch.equal(E_tuned, E_loop))
     n_changed = sum(1 for e in rep if e["best"] > 0)
+    decisions = {}
+    for e in rep:
+        if e["best"] >= 0:
+            key = "%dx%d" % tuple(e["tiles"][e["best"]])
+            d = decisions.setdefault(e["role"], {})
+            d[key] = d.get(key, 0) + 1
+        if args.stats:
+            print("[tune] %-10s M=%6d N=%6d K=%9d kchunk=%9d best=%s ms=%s" % (
+                e["role"], e["M"], e["N"], e["K"], e["kchunk"], e["tiles"][e["best"]] if e["best"] >= 0 else None,
+                " ".join("%dx%d:%.3f" % (t[0], t[1], m) for t, m in zip(e["tiles"], e["min_ms"]))), file=sys.stderr)
     print("[bench] per-fragment loop, autotuned: trial pass %.3f s, tuned %.3f s; %d of %d shapes off the default"
           % (t_trial, t_tuned, n_changed, len(rep)), file=sys.stderr, flush=True)
     rm.autotune_reset()
@@ -354,10 +380,14 @@ def bench_mbe3(args, torch, synth, rm, dev):
         "per_fragment_loop_tflops": round(total_alg / t_loop / 1e12, 4),
         "speedup_batch_vs_loop": round(t_loop / t_batch, 4),
         "speedup_graph_vs_loop": round(t_loop / t_graph, 4),
-        "autotune": {"loop_tuned_tflops": round(total_alg / t_tuned / 1e12, 4),
+        "autotune": {"batch_tuned_tflops": round(total_alg / t_batch_tuned / 1e12, 4),
+                     "speedup_tuned_vs_fixed_batch": round(t_batch / t_batch_tuned, 4),
+                     "batch_E_bitwise_equal_to_fixed": batch_tuned_bitwise,
+                     "loop_tuned_tflops": round(total_alg / t_tuned / 1e12, 4),
                      "loop_trial_pass_tflops": round(total_alg / t_trial / 1e12, 4),
                      "speedup_tuned_vs_fixed_loop": round(t_loop / t_tuned, 4),
-                     "shapes": len(rep), "shapes_off_default": n_changed, "E_bitwise_equal_to_fixed": tuned_bitwise},
+                     "shapes": len(rep), "shapes_off_default": n_changed, "E_bitwise_equal_to_fixed": tuned_bitwise,
+                     "chosen_tiles": decisions},
         "max_abs_dE_batch_vs_loop_Eh": dE,
         "roofline": {"bound": "mfma", "kernel": dom["name"] + " (grouped)", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None,

@@ -235,13 +235,20 @@ int rimp2_timing_collect(rimp2_kernel_stat* stats, int32_t capacity, int32_t* co
  * being captured into a graph.  The tile shape does not change the order in
  * which any output element is summed, so results are bitwise identical
  * whichever candidate runs.  The table is process-wide and thread-safe.
+ *
+ * Batches (rimp2_batch_run with opts->autotune set at rimp2_batch_create):
+ * each grouped GEMM launch of a wave has two candidate tiles, listed in the
+ * handle's tables for both, and is tuned the same way; its entry has vec = 2,
+ * M = fragments in the wave, N and K = work items of the two candidates and
+ * kchunk = a hash of the wave's fragment sizes, so handles built again for
+ * the same fragments (a later time step) reuse the decision.
  */
 typedef struct {
   char    role[32];      /* "ints_gemm", "gamma_gemm", "pab_gemm", "pij_gemm" */
   int32_t device;
   int32_t nvar;          /* candidates */
   int32_t best;          /* chosen candidate, -1 while trials are pending */
-  int32_t vec;           /* 16-byte loads eligible */
+  int32_t vec;           /* 16-byte loads eligible (2: grouped batch launch) */
   int64_t M, N, K, kchunk;
   int32_t tile_m[4], tile_n[4];   /* candidate tile shapes, [0] = default */
   int32_t timed[4];      /* completed trials per candidate */

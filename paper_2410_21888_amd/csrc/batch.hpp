@@ -33,7 +33,7 @@ struct AmpDesc {
   const double* ev;
   double* e_pair;
   const int32_t* status;
-  int32_t nocc, nvir, energy_only, pad;
+  int32_t nocc, nvir, energy_only;
 };
 struct ReduceDesc {
   double* out;
@@ -94,14 +94,15 @@ __global__ __launch_bounds__(256) void gap_check_grouped(const FragSmall* fs) {
   gap_check_block(f.eo, f.nocc, f.ev, f.nvir, f.status);
 }
 
-// one workgroup per occupied pair of every fragment (whole slab: k0 = 0)
+// one workgroup per occupied pair of every fragment (whole slab, k0 = 0,
+// blocks j < k not computed by the (ia|jb) GEMM: mirrored)
 __global__ __launch_bounds__(256) void amplitude_grouped(const AmpDesc* descs, const int64_t* prefix, int n) {
   const int f = find_problem(prefix, n, blockIdx.x);
   const AmpDesc d = descs[f];
   if (*d.status != 0) return;
   const int64_t u = blockIdx.x - prefix[f];
   const int kk = (int)(u / d.nocc), j = (int)(u - (int64_t)kk * d.nocc);
-  amplitude_block(d.V, d.T, d.eo, d.ev, d.nocc, d.nvir, 0, 0, d.nocc, 0, d.energy_only, nullptr, d.e_pair, kk, j);
+  amplitude_block(d.V, d.T, d.eo, d.ev, d.nocc, d.nvir, 0, 0, d.nocc, 2, d.energy_only, nullptr, d.e_pair, kk, j);
 }
 
 // prefix counts 256-element blocks per problem

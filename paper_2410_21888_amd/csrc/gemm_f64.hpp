@@ -22,7 +22,9 @@
 // halfway through them.
 //
 // Triangular launches (TRI): for a symmetric result only tiles with
-// tile_m <= tile_n are computed and each is also written transposed.
+// tile_m <= tile_n are computed; every element m < n is written at (m, n) and
+// (n, m), and elements m > n of diagonal tiles are not written, so the lower
+// triangle is always the mirror of the upper one whatever the tile size.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,13 +63,18 @@ struct GemmParams {
   // tile whose pairs are all marked in skip[k * skip_nocc + j] is not computed.
   const uint8_t* skip;
   int32_t skip_nvir, skip_k0, skip_j0, skip_nocc;
+  // pair_upper (same row/column to pair mapping): a tile all of whose pairs
+  // have j < k is not computed (their blocks are the transposes of computed ones).
+  int32_t pair_upper, pad;
 };
 
-// True when every occupied pair a tile touches is screened out (uniform).
+// True when the tile need not be computed (uniform): every occupied pair it
+// touches is screened out, or (pair_upper) has j < k.
 template <int BM, int BN>
 __device__ __forceinline__ bool tile_screened(const GemmParams& p, int tm, int tn) {
-  if (p.skip == nullptr) return false;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  if (p.pair_upper && p.skip_j0 + (min(p.N, n0 + BN) - 1) / p.skip_nvir < p.skip_k0 + m0 / p.skip_nvir) return true;
+  if (p.skip == nullptr) return false;
   const int64_t k_lo = m0 / p.skip_nvir, k_hi = (min(p.M, m0 + BM) - 1) / p.skip_nvir;
   const int64_t j_lo = n0 / p.skip_nvir, j_hi = (min(p.N, n0 + BN) - 1) / p.skip_nvir;
   for (int64_t k = k_lo; k <= k_hi; ++k)
@@ -274,8 +281,12 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
         const int64_t m = m0 + wm * WTM + i * 16 + 4 * r + (lane >> 4);
         const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
         if (m < p.M && n < p.N) {
-          C[m * p.ldc + n] = acc[i][j][r];
-          if (TRI && tm != tn) C[n * p.ldc + m] = acc[i][j][r];
+          if (!TRI) {
+            C[m * p.ldc + n] = acc[i][j][r];
+          } else if (m <= n) {   // every lower element is the mirror of an upper one
+            C[m * p.ldc + n] = acc[i][j][r];
+            if (m < n) C[n * p.ldc + m] = acc[i][j][r];
+          }
         }
       }
 }
@@ -330,6 +341,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_grouped(GemmGroup G) {
     const int z = u / ntiles;
     int tm, tn;
     decode_tile<TRI>(p, u - z * ntiles, tm, tn);
+    if (tile_screened<BM, BN>(p, tm, tn)) continue;
     gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI>(p, tm, tn, z, lds);
   }
 }

@@ -83,12 +83,82 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
   gap_check_block(eo, nocc, ev, nvir, status);
 }
 
+// Whole-slab pair (k, j > k) of a slab holding every occupied row and column
+// (k0 = j0 = 0, ncols = nocc) whose block (j, k) was not computed: V_jk is
+// V_kj transposed, and D_jk = D_kj, so this workgroup forms both pairs from
+// V_kj alone.  For positions (a, b) and (b, a) of the block:
+//   X_kj[a,b] = V_kj[a,b] / D[a,b]    X_kj[b,a] = V_kj[b,a] / D[b,a]
+//   X_jk[a,b] = V_kj[b,a] / D[a,b]    X_jk[b,a] = V_kj[a,b] / D[b,a]
+// with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b, T = 2X - X^T for each
+// pair, X written over V and T to the T slab in both blocks, and
+// e_kj = sum_ab T_kj V_kj (compensated) written to e_kj and e_jk.
+constexpr int AT = 32;
+__device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab, const double* eo, const double* ev,
+                                                       int nocc, int nvir, bool skip, double* e_pair, int k, int j) {
+  __shared__ double VP[AT][AT + 1], VQ[AT][AT + 1];
+  const int64_t ld = (int64_t)nocc * nvir;
+  double* bkj = S + ((int64_t)k * nvir * nocc + j) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
+  double* bjk = S + ((int64_t)j * nvir * nocc + k) * nvir;
+  double* tkj = Tslab + ((int64_t)k * nvir * nocc + j) * nvir;
+  double* tjk = Tslab + ((int64_t)j * nvir * nocc + k) * nvir;
+  const double ekj = eo[k] + eo[j];
+  const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;
+  const int nt = (nvir + AT - 1) / AT;
+  double sh = 0.0, sl = 0.0;
+  // one element position (a, b) given v = V_kj[a,b] and w = V_kj[b,a]
+  auto put = [&](int a, int b, double v, double w) {
+    const double dab = (ekj - ev[a]) - ev[b], dba = (ekj - ev[b]) - ev[a];
+    const double xkj = v / dab, xkj_t = w / dba, xjk = w / dab, xjk_t = v / dba;
+    const double t1 = 2.0 * xkj - xkj_t, t2 = 2.0 * xjk - xjk_t;
+    double p = t1 * v, e;
+    two_sum(sh, p, sh, e);
+    sl += e;
+    const int64_t o = (int64_t)a * ld + b;
+    bkj[o] = xkj; tkj[o] = t1;
+    bjk[o] = xjk; tjk[o] = t2;
+  };
+  for (int ta = 0; ta < nt; ++ta) {
+    for (int tb = ta; tb < nt; ++tb) {
+      const bool diag = (ta == tb);
+      double vP[4], vQ[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = tr0 + 8 * s;
+        const int a = ta * AT + r, b = tb * AT + tc, a2 = tb * AT + r, b2 = ta * AT + tc;
+        vP[s] = (!skip && a < nvir && b < nvir) ? bkj[(int64_t)a * ld + b] : 0.0;
+        vQ[s] = (!skip && !diag && a2 < nvir && b2 < nvir) ? bkj[(int64_t)a2 * ld + b2] : 0.0;
+        VP[r][tc] = vP[s];
+        VQ[r][tc] = vQ[s];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = tr0 + 8 * s;
+        const int a = ta * AT + r, b = tb * AT + tc;
+        if (a < nvir && b < nvir) put(a, b, vP[s], diag ? VP[tc][r] : VQ[tc][r]);
+        const int a2 = tb * AT + r, b2 = ta * AT + tc;
+        if (!diag && a2 < nvir && b2 < nvir) put(a2, b2, vQ[s], VP[tc][r]);
+      }
+      __syncthreads();
+    }
+  }
+  double h, l;
+  fast_two_sum(sh, sl, h, l);
+  block_dd_reduce(h, l);
+  if (t == 0) {
+    e_pair[(int64_t)k * nocc + j] = h + l;
+    e_pair[(int64_t)j * nocc + k] = h + l;
+  }
+}
+
 // Amplitude pass over one slab group.
 // V/X slab: element (kk, a, jj, b) at S[((kk*nvir + a)*ncols + jj)*nvir + b],
 // kk < g, jj < ncols, occupied pair (k, j) = (k0 + kk, j0 + jj).
-// One workgroup per pair.  With sym (energy only, slab holding j >= k0 only),
+// One workgroup per pair.  sym = 1 (energy only, slab holding j >= k0 only):
 // pairs with j < k are left to their mirror and e_kj is written to both e_kj
-// and e_jk (e_ij = e_ji).  A screened pair (pair_skip) writes e = 0 (and, unless
+// and e_jk (e_ij = e_ji).  sym = 2 (whole slab, blocks j < k not computed):
+// pairs j < k are left to their mirror, pairs j > k form both blocks
+// (amplitude_mirror_block; with energy_only as sym = 1).  A screened pair (pair_skip) writes e = 0 (and, unless
 // energy_only, zero X and T) without reading V.  For each pair of 32x32
 // tiles (ta <= tb) of the nvir x nvir block it reads V at (a,b) and (b,a),
 // forms X = V / D with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b in that
@@ -96,7 +166,6 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
 // X over V and T to the T slab (unless energy_only), and accumulates
 // e_kj = sum_ab T[a,b] V[a,b] with compensated per-thread sums and a fixed
 // reduction order.  pair_skip (may be null) zeroes skipped pairs.
-constexpr int AT = 32;
 __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
                                                 int nvir, int k0, int j0, int ncols, int sym, int energy_only,
                                                 const uint8_t* pair_skip, double* e_pair, int kk, int jj) {
@@ -107,6 +176,10 @@ __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const 
   double* blk = S + ((int64_t)kk * nvir * ncols + jj) * nvir;  // element (a,b) at blk[a*ld + b]
   double* tblk = Tslab + ((int64_t)kk * nvir * ncols + jj) * nvir;
   const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
+  if (sym == 2 && !energy_only && j > k) {
+    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k, j);
+    return;
+  }
   if (skip && energy_only) {
     if (threadIdx.x == 0) {
       e_pair[(int64_t)k * nocc + j] = 0.0;

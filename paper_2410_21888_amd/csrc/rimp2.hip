@@ -11,6 +11,13 @@
 //   -> compensated E = sum e_ij.
 // Slab layout [kk][a][j][b]: the (ia|jb) and Gamma GEMMs see plain row-major
 // matrices; P_ab and P_ij read the same slabs with a two-level reduction index.
+// P_ab and P_ij are symmetric, so their GEMMs compute upper-triangular tiles
+// and write each also transposed.  For P_ij every slab's contribution is
+// symmetric.  For P_ab only the sum over both orders of each pair is
+// (T_kj X_kj^T + T_jk X_jk^T = 2(X X^T + X^T X) - (X X + (X X)^T) with
+// X = X_kj), so the mirrored partials of a slab group are not its own lower
+// triangle; but the mirror of a sum is the sum of the mirrors, and the total
+// over all groups is symmetric, so the accumulated lower triangle is exact.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdarg.h>
@@ -93,6 +100,15 @@ constexpr int kBK = 16;
 constexpr int64_t kSlots = 512;       // resident GEMM workgroups: 2 per CU on 256 CUs
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// A dispatch's grid size is a 32-bit count of work-items (workgroups x 256 here).
+constexpr int64_t kMaxWorkgroups = 0xffffffffLL / 256;
+int check_grid(int64_t wgs, const char* what) {
+  if (wgs <= 0 || wgs > kMaxWorkgroups)
+    return fail(RIMP2_EINVAL, "%s grid of %lld workgroups is out of range (1..%lld)", what, (long long)wgs,
+                (long long)kMaxWorkgroups);
+  return RIMP2_OK;
+}
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Split-K factor for a launch of `tiles` output tiles over reduction length K:
@@ -160,9 +176,9 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
     g = std::max<int64_t>(1, std::min<int64_t>(g, nocc));
   }
   p->g = g;
-  // split-K factors (see choose_splits); P_ij uses upper-triangular tiles
-  const int64_t tab = pab_tile96(nvir) ? 96 : kTile, tij = cdiv(nocc, kSmallTile);
-  p->s_ab = density ? choose_splits(cdiv(nvir, tab) * cdiv(nvir, tab), g * nocc * nvir) : 0;
+  // split-K factors (see choose_splits); P_ab and P_ij use upper-triangular tiles
+  const int64_t tab = cdiv(nvir, pab_tile96(nvir) ? 96 : kTile), tij = cdiv(nocc, kSmallTile);
+  p->s_ab = density ? choose_splits(tab * (tab + 1) / 2, g * nocc * nvir) : 0;
   p->s_ij = density ? choose_splits(tij * (tij + 1) / 2, g * nvir * nvir) : 0;
   p->s_gam = gamma ? choose_splits(cdiv(g * nvir, kTile) * cdiv(naux, kTile), nocc * nvir) : 0;
   size_t off = 0;
@@ -187,6 +203,11 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
     }
   }
   p->total = off;
+  int rc;
+  if ((rc = check_grid(g * nocc, "amplitude"))) return rc;
+  if (gamma && p->s_gam > 1 && (rc = check_grid(cdiv(g * nvir * naux, 256), "reduction"))) return rc;
+  if (p->split && ((rc = check_grid(nocc * nvir, "digit split")) || (rc = check_grid(cdiv(p->kpg, 32), "digit split"))))
+    return rc;
   return RIMP2_OK;
 }
 
@@ -213,9 +234,18 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   if (TRI && (gp.M != gp.N || BM != BN)) return fail(RIMP2_EINVAL, "triangular GEMM needs a square tile grid");
   const int64_t tiles = TRI ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
   const int64_t nwg = tiles * gp.splits;
-  if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "GEMM grid too large (%lld workgroups)", (long long)nwg);
+  if (int rc = check_grid(nwg, "GEMM")) return rc;
   const bool vec = gemm_vec(gp, NC);
-  const double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
+  double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
+  if (gp.pair_upper) {  // tiles not skipped: those with a pair j >= k (see tile_screened)
+    int64_t kept = 0;
+    for (int64_t tm = 0; tm < gp.tiles_m; ++tm) {
+      const int64_t k_lo = gp.skip_k0 + tm * BM / gp.skip_nvir;
+      const int64_t first = std::max<int64_t>(0, cdiv((k_lo - gp.skip_j0) * gp.skip_nvir - BN + 1, BN));
+      kept += std::max<int64_t>(0, gp.tiles_n - first);
+    }
+    ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
+  }
   return traced(role, af, ef, ab, st, [&] {
     if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
@@ -265,9 +295,9 @@ int launch_role(int role, int bm, const GemmParams& gp, hipStream_t st, double a
       return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA, false>(gp, st, role, af, ab)
                       : launch_gemm<128, 128, true, ROLE_GAMMA, false>(gp, st, role, af, ab);
     case R_PAB:
-      return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, false>(gp, st, role, af, ab)
-             : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, false>(gp, st, role, af, ab)
-                        : launch_gemm<128, 128, false, ROLE_PAB, false>(gp, st, role, af, ab);
+      return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, true>(gp, st, role, af, ab)
+             : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, true>(gp, st, role, af, ab)
+                        : launch_gemm<128, 128, false, ROLE_PAB, true>(gp, st, role, af, ab);
     case R_PIJ:
       return bm == 32    ? launch_gemm<32, 32, false, ROLE_PIJ, true>(gp, st, role, af, ab)
              : bm == 128 ? launch_gemm<128, 128, false, ROLE_PIJ, true>(gp, st, role, af, ab)
@@ -341,22 +371,17 @@ void tune_poll(Tuner& U, TuneEntry& e) {
   e.best = best;
 }
 
-// Launches the GEMM of `role`: the default tile shape, or with autotuning the
-// shape's chosen candidate (a candidate still owed a trial, bracketed by
-// events, while the choice is open and the stream is not capturing).
-int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, double af, double ab) {
-  TileShape c[kTuneVars];
-  const int nvar = tile_candidates(role, gp, c);
-  if (!autotune || nvar < 2) return launch_role(role, c[0].bm, gp, st, af, ab);
+// Runs launch(v) for the candidate v of `key` that the tuner picks (see
+// tune_poll): the decided one, else a candidate still owed a trial (bracketed
+// by events on st, unless st is capturing), else candidate 0.
+template <class F>
+int tuned(const TuneKey& key, int nvar, const TileShape* cand, hipStream_t st, F&& launch) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
     (void)hipGetLastError();
     cs = hipStreamCaptureStatusActive;
   }
   const bool capturing = cs != hipStreamCaptureStatusNone;
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  const TuneKey key{dev, role, gemm_vec(gp, role == R_GAMMA) ? 1 : 0, gp.M, gp.N, gp.K, gp.kchunk};
   Tuner& U = tuner();
   int v = 0;
   bool trial = false;
@@ -366,7 +391,7 @@ int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, 
     TuneEntry& e = U.tab[key];
     if (e.nvar == 0) {
       e.nvar = nvar;
-      for (int i = 0; i < nvar; ++i) e.cand[i] = c[i];
+      for (int i = 0; i < nvar; ++i) e.cand[i] = cand[i];
     }
     e.uses += 1;
     if (!capturing) tune_poll(U, e);
@@ -390,7 +415,7 @@ int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, 
     if (trial) e.launched[v] += 1;
   }
   const bool rec0 = trial && hipEventRecord(ev[0], st) == hipSuccess;
-  const int rc = launch_role(role, c[v].bm, gp, st, af, ab);
+  const int rc = launch(v);
   if (trial) {
     const bool ok = rec0 && rc == RIMP2_OK && hipEventRecord(ev[1], st) == hipSuccess;
     if (!ok) (void)hipGetLastError();
@@ -405,6 +430,18 @@ int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, 
     }
   }
   return rc;
+}
+
+// Launches the GEMM of `role`: the default tile shape, or with autotuning the
+// shape's tuned candidate.
+int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, double af, double ab) {
+  TileShape c[kTuneVars];
+  const int nvar = tile_candidates(role, gp, c);
+  if (!autotune || nvar < 2) return launch_role(role, c[0].bm, gp, st, af, ab);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const TuneKey key{dev, role, gemm_vec(gp, role == R_GAMMA) ? 1 : 0, gp.M, gp.N, gp.K, gp.kchunk};
+  return tuned(key, nvar, c, st, [&](int v) { return launch_role(role, c[v].bm, gp, st, af, ab); });
 }
 
 
@@ -450,7 +487,7 @@ int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32
   op.tiles_m = (int32_t)cdiv(M, 64); op.tiles_n = (int32_t)cdiv(N, 64); op.group_m = 8;
   op.status = status;
   const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
-  if (nwg <= 0 || nwg > 0x7fffffff) return fail(RIMP2_EINVAL, "split GEMM grid too large");
+  if (int rc = check_grid(nwg, "split GEMM")) return rc;
   const double ef = 2.0 * (double)M * N * kp;
   return traced(role, af, ef, ab, st, [&] { RIMP2_SWITCH_S(S, launch_oz8<SS>(op, st)); });
 }
@@ -472,6 +509,9 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
        })))
     return rc;
   const bool energy_only = !(P.gamma || P.density);
+  // whole slab (one group of every occupied orbital): blocks (k, j < k) are
+  // not computed and the amplitude pass forms them from their transposes
+  const bool mirror = !P.split && !energy_only && P.g >= nocc;
   int8_t* dbv = (int8_t*)(ws + P.off_dbv);
   int32_t* exv = (int32_t*)(ws + P.off_ev);
   int8_t* dbg = (int8_t*)(ws + P.off_dbg);
@@ -516,6 +556,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       gp.C = V; gp.ldc = Lc; gp.split_stride = 0; gp.status = status;
       gp.skip = skip; gp.skip_nvir = (int32_t)nvir; gp.skip_k0 = (int32_t)k0; gp.skip_j0 = (int32_t)j0;
       gp.skip_nocc = (int32_t)nocc;
+      gp.pair_upper = (energy_only || mirror) ? 1 : 0;
       // algorithmic FLOPs: unordered pairs whose first orbital is in the group
       // (energy only: exactly the pairs (k, j >= k) computed; otherwise the
       // unordered-pair share of the ordered pairs computed)
@@ -532,7 +573,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
     }
     if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
            hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols)), dim3(256), 0, st, V, T, eo, ev,
-                              (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, energy_only ? 1 : 0,
+                              (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, energy_only ? 1 : (mirror ? 2 : 0),
                               energy_only ? 1 : 0, skip, ep, status);
          })))
       return rc;
@@ -634,15 +675,19 @@ struct Wave {
   size_t bytes = 0;             // tables + fragment partitions
   // offsets within the tables
   size_t o_fs, o_idx, o_amp, o_amp_pre, o_red, o_red_pre, o_cnt;
-  size_t o_g[8], o_pre[8];      // GEMM lists: ints v/nv, gamma v/nv, pab v/nv, pij v/nv
-  int n_g[8];
-  int64_t items_g[8];
+  // GEMM lists, index glist(role, candidate tile, 16-byte loads): every GEMM
+  // is listed once per candidate tile shape (kBatchTile)
+  size_t o_g[16], o_pre[16];
+  int n_g[16];
+  int64_t items_g[16];
+  uint64_t sig = 0;             // hash of the wave's fragment sizes (autotuner key)
   int namp, nred_ab, nred_ij;
   int64_t amp_blocks, red_blocks_ab, red_blocks_ij;
 };
 }  // namespace
 
 struct rimp2_batch_s {
+  bool autotune = false;
   std::vector<rimp2_frag_desc> d;
   std::vector<int32_t> solo;       // fragments run alone
   std::vector<Plan> plan;          // per fragment (solo: own plan; grouped: full-slab plan)
@@ -662,6 +707,12 @@ bool kop_vec_rel(const KOperand& o, int64_t K) {
   const bool plain = o.kdiv >= K;
   return aligned16(o.base) && o.rs % 2 == 0 && (plain || (o.kdiv % 2 == 0 && o.ks1 % 2 == 0));
 }
+
+// Grouped GEMM roles of a wave, their two candidate square tiles (default
+// first) and list index.
+const int kBatchRole[4] = {R_INTS, R_GAMMA, R_PAB, R_PIJ};
+const int kBatchTile[4][2] = {{128, 64}, {128, 64}, {128, 64}, {64, 32}};
+int glist(int rho, int cand, bool vec) { return (rho * 2 + cand) * 2 + (vec ? 0 : 1); }
 
 // tiles, splits and group size of a GEMM, as launch_gemm sets them
 int64_t finalize_gemm(GemmParams& gp, int BM, int BN, bool tri) {
@@ -686,6 +737,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
   if (opts && opts->precision != RIMP2_FP64) return fail(RIMP2_ENOTSUP, "batches run in FP64 only");
   if (opts && opts->pair_skip) return fail(RIMP2_ENOTSUP, "pair_skip is not supported for batches");
   B->d.assign(d, d + nfrag);
+  B->autotune = opts && opts->autotune;
   B->plan.resize(nfrag);
   const size_t budget = (opts && opts->slab_budget_bytes) ? opts->slab_budget_bytes : (size_t)64 << 30;
   std::vector<int32_t> order(nfrag), grouped;
@@ -737,11 +789,11 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     W.o_amp_pre = place(t, sizeof(int64_t) * (n + 1));
     W.o_red = place(t, sizeof(ReduceDesc) * 2 * n);
     W.o_red_pre = place(t, sizeof(int64_t) * (2 * n + 1));
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < 16; ++r) {
       W.o_g[r] = place(t, sizeof(GemmParams) * n);
       W.o_pre[r] = place(t, sizeof(int64_t) * (n + 1));
     }
-    W.o_cnt = place(t, 8 * sizeof(unsigned long long));
+    W.o_cnt = place(t, 16 * sizeof(unsigned long long));
     W.tab_bytes = t;
     W.host_off = tab;
     tab = align_up(tab + t);
@@ -756,8 +808,19 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     std::vector<int64_t> amp_pre(n + 1, 0);
     std::vector<ReduceDesc> red;
     std::vector<int64_t> red_pre(1, 0);
-    GemmList gl[8];
+    GemmList gl[16];
     for (auto& l : gl) l.prefix.assign(1, 0);
+    // every GEMM goes to the lists of both candidate tiles of its role
+    auto add = [&](int rho, const GemmParams& g0, bool vec) {
+      for (int c = 0; c < 2; ++c) {
+        GemmParams g = g0;
+        const int64_t items = finalize_gemm(g, kBatchTile[rho][c], kBatchTile[rho][c], rho >= 2);
+        GemmList& l = gl[glist(rho, c, vec)];
+        l.p.push_back(g);
+        l.prefix.push_back(l.prefix.back() + items);
+      }
+    };
+    uint64_t sig = 1469598103934665603ull;  // FNV-1a over the fragment sizes and outputs
     size_t poff = tab;   // fragment partitions follow all tables (shared by the waves)
     for (int i = 0; i < n; ++i) {
       const int32_t f = W.frags[i];
@@ -766,13 +829,14 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       const size_t base = poff;
       poff = align_up(poff + P.total);
       const int64_t nocc = q.nocc, nvir = q.nvir, naux = q.naux, L = nocc * nvir;
+      for (int64_t w : {nocc, nvir, naux, (int64_t)P.gamma, (int64_t)P.density}) sig = (sig ^ (uint64_t)w) * 1099511628211ull;
       int32_t* status = relp<int32_t>(base + P.off_status);
       double* V = relp<double>(base + P.off_V);
       double* T = relp<double>(base + P.off_T);
       double* ep = q.e_pair ? q.e_pair : relp<double>(base + P.off_e);
       fs[i] = FragSmall{q.eps_occ, q.eps_vir, ep, q.E, status, q.nocc, q.nvir};
       idx[i] = f;
-      amp[i] = AmpDesc{V, T, q.eps_occ, q.eps_vir, ep, status, q.nocc, q.nvir, (P.gamma || P.density) ? 0 : 1, 0};
+      amp[i] = AmpDesc{V, T, q.eps_occ, q.eps_vir, ep, status, q.nocc, q.nvir, (P.gamma || P.density) ? 0 : 1};
       amp_pre[i + 1] = amp_pre[i] + nocc * nocc;
       {  // (ia|jb)
         GemmParams gp{};
@@ -780,9 +844,8 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         gp.A = KOperand{q.B, naux, INT64_MAX, 0};
         gp.Bk = KOperand{q.B, naux, INT64_MAX, 0};
         gp.C = V; gp.ldc = L; gp.status = status;
-        const int64_t items = finalize_gemm(gp, kTile, kTile, false);
-        const int r = (kop_vec_rel(gp.A, gp.K) && kop_vec_rel(gp.Bk, gp.K)) ? 0 : 1;
-        gl[r].p.push_back(gp); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        gp.skip_nvir = (int32_t)nvir; gp.skip_nocc = (int32_t)nocc; gp.pair_upper = 1;
+        add(0, gp, kop_vec_rel(gp.A, gp.K) && kop_vec_rel(gp.Bk, gp.K));
       }
       if (P.gamma) {
         GemmParams gp{};
@@ -790,9 +853,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         gp.A = KOperand{T, L, INT64_MAX, 0};
         gp.Bn = NOperand{q.B, naux};
         gp.C = q.Gamma; gp.ldc = naux; gp.status = status;
-        const int64_t items = finalize_gemm(gp, kTile, kTile, false);
-        const int r = (kop_vec_rel(gp.A, gp.K) && aligned16(q.B) && naux % 2 == 0) ? 2 : 3;
-        gl[r].p.push_back(gp); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        add(1, gp, kop_vec_rel(gp.A, gp.K) && aligned16(q.B) && naux % 2 == 0);
       }
       if (P.density) {
         double* Wab = relp<double>(base + P.off_pab);
@@ -802,17 +863,15 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         ga.A = KOperand{T, L, L, nvir * L};
         ga.Bk = KOperand{V, L, L, nvir * L};
         ga.C = Wab; ga.ldc = nvir; ga.split_stride = nvir * nvir; ga.status = status;
-        int64_t items = finalize_gemm(ga, kTile, kTile, false);
-        int r = (kop_vec_rel(ga.A, ga.K) && kop_vec_rel(ga.Bk, ga.K)) ? 4 : 5;
-        gl[r].p.push_back(ga); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        add(2, ga, kop_vec_rel(ga.A, ga.K) && kop_vec_rel(ga.Bk, ga.K));
+        (void)finalize_gemm(ga, kTile, kTile, false);   // splits for the reduction
         GemmParams gi{};
         gi.M = nocc; gi.N = nocc; gi.K = nocc * nvir * nvir; gi.kchunk = cdiv(gi.K, P.s_ij);
         gi.A = KOperand{T, nvir, nvir, L};
         gi.Bk = KOperand{V, nvir, nvir, L};
         gi.C = Wij; gi.ldc = nocc; gi.split_stride = nocc * nocc; gi.status = status;
-        items = finalize_gemm(gi, kSmallTile, kSmallTile, true);
-        r = (kop_vec_rel(gi.A, gi.K) && kop_vec_rel(gi.Bk, gi.K)) ? 6 : 7;
-        gl[r].p.push_back(gi); gl[r].prefix.push_back(gl[r].prefix.back() + items);
+        add(3, gi, kop_vec_rel(gi.A, gi.K) && kop_vec_rel(gi.Bk, gi.K));
+        (void)finalize_gemm(gi, kSmallTile, kSmallTile, true);
         ReduceDesc ra{q.P_ab, Wab, status, nvir, nvir, nvir * nvir, nvir, nvir, 1.0, ga.splits, 0};
         ReduceDesc ri{q.P_ij, Wij, status, nocc, nocc, nocc * nocc, nocc, nocc, -1.0, gi.splits, 0};
         red.push_back(ra); red_pre.push_back(red_pre.back() + cdiv(nvir * nvir, 256));
@@ -825,7 +884,8 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     W.amp_blocks = amp_pre[n];
     W.nred_ab = (int)red.size();
     W.red_blocks_ab = red_pre.back();
-    for (int r = 0; r < 8; ++r) { W.n_g[r] = (int)gl[r].p.size(); W.items_g[r] = gl[r].prefix.back(); }
+    for (int r = 0; r < 16; ++r) { W.n_g[r] = (int)gl[r].p.size(); W.items_g[r] = gl[r].prefix.back(); }
+    W.sig = sig;
     char* blob = B->blob.data() + W.host_off;
     auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) memcpy(blob + off, src, bytes); };
     put(W.o_fs, fs.data(), sizeof(FragSmall) * n);
@@ -834,7 +894,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     put(W.o_amp_pre, amp_pre.data(), sizeof(int64_t) * (n + 1));
     put(W.o_red, red.data(), sizeof(ReduceDesc) * red.size());
     put(W.o_red_pre, red_pre.data(), sizeof(int64_t) * red_pre.size());
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < 16; ++r) {
       put(W.o_g[r], gl[r].p.data(), sizeof(GemmParams) * gl[r].p.size());
       put(W.o_pre[r], gl[r].prefix.data(), sizeof(int64_t) * gl[r].prefix.size());
     }
@@ -851,6 +911,26 @@ int launch_grouped(const GemmGroup& G, int64_t items, int role, hipStream_t st) 
   return traced(role, 0, 0, 0, st, [&] {
     hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, kBK, NC, ROLE, VEC, TRI>), dim3((unsigned)grid), dim3(256), 0, st, G);
   });
+}
+
+// One grouped launch of batch role rho with candidate tile c (kBatchTile) over
+// its list with or without 16-byte loads.
+int launch_group_list(int rho, int c, bool vec, const GemmGroup& G, int64_t items, hipStream_t st) {
+  const int role = kBatchRole[rho];
+#define RIMP2_G(BM, NC, ROLE, TRI)                                                        \
+  return vec ? launch_grouped<BM, BM, NC, ROLE, true, TRI>(G, items, role, st)            \
+             : launch_grouped<BM, BM, NC, ROLE, false, TRI>(G, items, role, st)
+  switch (rho * 2 + c) {
+    case 0: RIMP2_G(128, false, ROLE_INTS, false);
+    case 1: RIMP2_G(64, false, ROLE_INTS, false);
+    case 2: RIMP2_G(128, true, ROLE_GAMMA, false);
+    case 3: RIMP2_G(64, true, ROLE_GAMMA, false);
+    case 4: RIMP2_G(128, false, ROLE_PAB, true);
+    case 5: RIMP2_G(64, false, ROLE_PAB, true);
+    case 6: RIMP2_G(64, false, ROLE_PIJ, true);
+    default: RIMP2_G(32, false, ROLE_PIJ, true);
+  }
+#undef RIMP2_G
 }
 
 // upload: 0 = tables already in the workspace, 1 = copy them from B->host (pinned) on the stream
@@ -883,7 +963,7 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
     auto at = [&](size_t o) { return ws + W.host_off + o; };
     if ((rc = traced(R_STATUS, 0, 0, 0, st, [&] {
            // relocate every table (GEMM lists are contiguous per role; relocate each list)
-           for (int r = 0; r < 8; ++r)
+           for (int r = 0; r < 16; ++r)
              if (W.n_g[r])
                hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(W.n_g[r], 256)), dim3(256), 0, st, ws,
                                   (GemmParams*)at(W.o_g[r]), W.n_g[r], (AmpDesc*)nullptr, 0, (ReduceDesc*)nullptr, 0,
@@ -892,7 +972,7 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
            hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, ws, gp0, 0,
                               (AmpDesc*)at(W.o_amp), n, (ReduceDesc*)at(W.o_red), W.nred_ab, (FragSmall*)at(W.o_fs),
                               n);
-           hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt), 8);
+           hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt), 16);
            hipLaunchKernelGGL(gap_check_grouped, dim3((unsigned)n), dim3(256), 0, st, (const FragSmall*)at(W.o_fs));
          })))
       return rc;
@@ -900,21 +980,34 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
       return GemmGroup{(const GemmParams*)at(W.o_g[r]), (const int64_t*)at(W.o_pre[r]), W.n_g[r],
                        (unsigned long long*)at(W.o_cnt) + r};
     };
-    if ((rc = launch_grouped<kTile, kTile, false, ROLE_INTS, true, false>(grp(0), W.items_g[0], R_INTS, st))) return rc;
-    if ((rc = launch_grouped<kTile, kTile, false, ROLE_INTS, false, false>(grp(1), W.items_g[1], R_INTS, st))) return rc;
+    // each GEMM role: the lists of one candidate tile (with autotuning the
+    // tuned one for this wave's fragment sizes)
+    auto run_role = [&](int rho) -> int {
+      const int64_t i0 = W.items_g[glist(rho, 0, true)] + W.items_g[glist(rho, 0, false)];
+      if (i0 == 0) return RIMP2_OK;
+      auto launch = [&](int c) -> int {
+        for (int vec = 1; vec >= 0; --vec) {
+          const int li = glist(rho, c, vec != 0);
+          const int r = launch_group_list(rho, c, vec != 0, grp(li), W.items_g[li], st);
+          if (r) return r;
+        }
+        return RIMP2_OK;
+      };
+      if (!B->autotune) return launch(0);
+      int dev = 0;
+      HIP_TRY(hipGetDevice(&dev));
+      const int64_t i1 = W.items_g[glist(rho, 1, true)] + W.items_g[glist(rho, 1, false)];
+      const TuneKey key{dev, kBatchRole[rho], 2, n, i0, i1, (int64_t)(W.sig >> 1)};
+      const TileShape cand[2] = {{kBatchTile[rho][0], kBatchTile[rho][0]}, {kBatchTile[rho][1], kBatchTile[rho][1]}};
+      return tuned(key, 2, cand, st, launch);
+    };
+    if ((rc = run_role(0))) return rc;
     if ((rc = traced(R_AMP, 0, 0, 0, st, [&] {
            hipLaunchKernelGGL(amplitude_grouped, dim3((unsigned)W.amp_blocks), dim3(256), 0, st,
                               (const AmpDesc*)at(W.o_amp), (const int64_t*)at(W.o_amp_pre), n);
          })))
       return rc;
-    if ((rc = launch_grouped<kTile, kTile, true, ROLE_GAMMA, true, false>(grp(2), W.items_g[2], R_GAMMA, st))) return rc;
-    if ((rc = launch_grouped<kTile, kTile, true, ROLE_GAMMA, false, false>(grp(3), W.items_g[3], R_GAMMA, st))) return rc;
-    if ((rc = launch_grouped<kTile, kTile, false, ROLE_PAB, true, false>(grp(4), W.items_g[4], R_PAB, st))) return rc;
-    if ((rc = launch_grouped<kTile, kTile, false, ROLE_PAB, false, false>(grp(5), W.items_g[5], R_PAB, st))) return rc;
-    if ((rc = launch_grouped<kSmallTile, kSmallTile, false, ROLE_PIJ, true, true>(grp(6), W.items_g[6], R_PIJ, st)))
-      return rc;
-    if ((rc = launch_grouped<kSmallTile, kSmallTile, false, ROLE_PIJ, false, true>(grp(7), W.items_g[7], R_PIJ, st)))
-      return rc;
+    if ((rc = run_role(1)) || (rc = run_role(2)) || (rc = run_role(3))) return rc;
     if (W.nred_ab && (rc = traced(R_REDUCE, 0, 0, 0, st, [&] {
                         hipLaunchKernelGGL(reduce_grouped, dim3((unsigned)W.red_blocks_ab), dim3(256), 0, st,
                                            (const ReduceDesc*)at(W.o_red), (const int64_t*)at(W.o_red_pre), W.nred_ab);

@@ -13,6 +13,8 @@ using namespace rimp2;
 
 namespace {
 
+// a dispatch's grid size is a 32-bit count of work-items
+constexpr int64_t kMaxItems = 0xffffffffLL;
 constexpr int H = RIMP2_MLP_HIDDEN, NIN = RIMP2_MLP_IN, NP = RIMP2_MLP_PARAMS;
 constexpr int OW1 = 0, OB1 = OW1 + H * NIN, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H;
 
@@ -286,6 +288,7 @@ int rimp2_pair_features(int32_t nocc, int32_t nvir, int32_t naux, const double* 
 int rimp2_mlp_forward(int64_t n, const double* x, const double* params, double* y, void* stream) {
   if (n < 0 || (n > 0 && (!x || !params || !y))) return fail(RIMP2_EINVAL, "bad forward arguments");
   if (n == 0) return RIMP2_OK;
+  if (cdiv(n, FS) * 64 > kMaxItems) return fail(RIMP2_EINVAL, "n = %lld is too large for one launch", (long long)n);
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)cdiv(n, FS)), dim3(64), 0, (hipStream_t)stream, n, x, params,
                      y);
   HIP_TRY(hipGetLastError());
@@ -300,6 +303,7 @@ int rimp2_mlp_loss_grad(int64_t n, const double* x, const double* target, const 
   if (workspace_bytes < rimp2_mlp_workspace_size(n)) return fail(RIMP2_ENOMEM, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
   const int64_t nw = cdiv(n, BS);
+  if (nw * 64 > kMaxItems) return fail(RIMP2_EINVAL, "n = %lld is too large for one launch", (long long)n);
   hipLaunchKernelGGL(mlp_backward_kernel, dim3((unsigned)nw), dim3(64), 0, st, n, x, target, params,
                      (double*)workspace);
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)cdiv(NP + 1, 256)), dim3(256), 0, st, (const double*)workspace,
@@ -321,6 +325,7 @@ int rimp2_mlp_adam(const double* grad, double* params, double* m, double* v, int
 int rimp2_log_energy(int64_t n, const double* e, double* out, void* stream) {
   if (n < 0 || (n > 0 && (!e || !out))) return fail(RIMP2_EINVAL, "bad arguments");
   if (n == 0) return RIMP2_OK;
+  if (cdiv(n, 256) * 256 > kMaxItems) return fail(RIMP2_EINVAL, "n = %lld is too large for one launch", (long long)n);
   hipLaunchKernelGGL(log_energy_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, (hipStream_t)stream, n, e, out);
   HIP_TRY(hipGetLastError());
   return RIMP2_OK;

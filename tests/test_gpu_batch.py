@@ -108,3 +108,35 @@ def test_batch_graph_capture_replays():
             for k, v in e.items():
                 assert torch.equal(d[k], v), (rep, k)
     b.close()
+
+
+def test_batch_autotune_bitwise_and_decides():
+    frags, refs = make_frags(MBE_LIKE)
+    outs = ("E", "Gamma", "P_ij", "P_ab", "e_pair")
+    b0 = rm.Batch(frags)
+    ws = torch.empty(b0.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    b0.run(ws)
+    torch.cuda.synchronize()
+    check(frags, refs)
+    ref = [{k: d[k].clone() for k in outs} for d in frags]
+    b0.close()
+    rm.autotune_reset()
+    b = rm.Batch(frags, opts=rm.make_opts(autotune=True))
+    assert b.workspace_bytes <= ws.numel()
+    for call in range(6):
+        say("autotuned batch run %d" % call)
+        for d in frags:
+            for k in outs:
+                d[k].fill_(float("nan"))
+        b.run(ws)
+        torch.cuda.synchronize()
+        for d, r in zip(frags, ref):
+            for k in outs:
+                assert torch.equal(d[k], r[k]), (call, k)
+    rep = [e for e in rm.autotune_report() if e["vec"] == 2]
+    assert {e["role"] for e in rep} == {"ints_gemm", "gamma_gemm", "pab_gemm", "pij_gemm"}
+    for e in rep:
+        say("grouped %s: tiles %s timed %s ms %s -> %s" % (e["role"], e["tiles"], e["timed"], e["min_ms"], e["best"]))
+        assert e["best"] >= 0 and e["timed"] == [2, 2], e
+    b.close()
+    rm.autotune_reset()
