@@ -83,6 +83,45 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
   gap_check_block(eo, nocc, ev, nvir, status);
 }
 
+// LDS-only workgroup barrier: orders LDS accesses across the workgroup but,
+// unlike __syncthreads, does not wait for outstanding global loads, so the
+// next tile's prefetch stays in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Tile pairs (ta <= tb) of an nt x nt tile grid in row order: q -> (ta, tb).
+__device__ __forceinline__ void tile_pair_at(int q, int nt, int& ta, int& tb) {
+  ta = 0;
+  while (q >= nt - ta) { q -= nt - ta; ++ta; }
+  tb = ta + q;
+}
+__device__ __forceinline__ void tile_pair_next(int nt, int& ta, int& tb) {
+  if (++tb == nt) { ++ta; tb = ta; }
+}
+
+// Writes a workgroup's pair-energy sum: to its (hi, lo) partial slot when the
+// pair is split over several workgroups (epart), else to e_kj (and e_jk).
+__device__ __forceinline__ void put_pair_energy(double sh, double sl, double* e_pair, int nocc, int k, int j,
+                                                bool mirror, double* epart) {
+  double h, l;
+  fast_two_sum(sh, sl, h, l);
+  block_dd_reduce(h, l);
+  if (threadIdx.x == 0) {
+    if (epart) {
+      epart[0] = h;
+      epart[1] = l;
+    } else {
+      e_pair[(int64_t)k * nocc + j] = h + l;
+      if (mirror) e_pair[(int64_t)j * nocc + k] = h + l;
+    }
+  }
+}
+
+constexpr int AT = 32;
+
 // Whole-slab pair (k, j > k) of a slab holding every occupied row and column
 // (k0 = j0 = 0, ncols = nocc) whose block (j, k) was not computed: V_jk is
 // V_kj transposed, and D_jk = D_kj, so this workgroup forms both pairs from
@@ -91,11 +130,13 @@ __global__ __launch_bounds__(256) void gap_check_kernel(const double* eo, int no
 //   X_jk[a,b] = V_kj[b,a] / D[a,b]    X_jk[b,a] = V_kj[a,b] / D[b,a]
 // with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b, T = 2X - X^T for each
 // pair, X written over V and T to the T slab in both blocks, and
-// e_kj = sum_ab T_kj V_kj (compensated) written to e_kj and e_jk.
-constexpr int AT = 32;
+// e_kj = sum_ab T_kj V_kj (compensated) written to e_kj and e_jk.  The
+// workgroup covers tile pairs [q0, q1) of the block.  VP and VQ are two
+// AT x (AT+1) LDS tiles of the caller.
 __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab, const double* eo, const double* ev,
-                                                       int nocc, int nvir, bool skip, double* e_pair, int k, int j) {
-  __shared__ double VP[AT][AT + 1], VQ[AT][AT + 1];
+                                                       int nocc, int nvir, bool skip, double* e_pair, int k, int j,
+                                                       int q0, int q1, double* epart, double (*VP)[AT + 1],
+                                                       double (*VQ)[AT + 1]) {
   const int64_t ld = (int64_t)nocc * nvir;
   double* bkj = S + ((int64_t)k * nvir * nocc + j) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
   double* bjk = S + ((int64_t)j * nvir * nocc + k) * nvir;
@@ -117,148 +158,183 @@ __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab,
     bkj[o] = xkj; tkj[o] = t1;
     bjk[o] = xjk; tjk[o] = t2;
   };
-  for (int ta = 0; ta < nt; ++ta) {
-    for (int tb = ta; tb < nt; ++tb) {
-      const bool diag = (ta == tb);
-      double vP[4], vQ[4];
+  double nP[4], nQ[4];
+  auto fetch = [&](int ta, int tb) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = tr0 + 8 * s;
-        const int a = ta * AT + r, b = tb * AT + tc, a2 = tb * AT + r, b2 = ta * AT + tc;
-        vP[s] = (!skip && a < nvir && b < nvir) ? bkj[(int64_t)a * ld + b] : 0.0;
-        vQ[s] = (!skip && !diag && a2 < nvir && b2 < nvir) ? bkj[(int64_t)a2 * ld + b2] : 0.0;
-        VP[r][tc] = vP[s];
-        VQ[r][tc] = vQ[s];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = tr0 + 8 * s;
-        const int a = ta * AT + r, b = tb * AT + tc;
-        if (a < nvir && b < nvir) put(a, b, vP[s], diag ? VP[tc][r] : VQ[tc][r]);
-        const int a2 = tb * AT + r, b2 = ta * AT + tc;
-        if (!diag && a2 < nvir && b2 < nvir) put(a2, b2, vQ[s], VP[tc][r]);
-      }
-      __syncthreads();
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      const int a = ta * AT + r, b = tb * AT + tc, a2 = tb * AT + r, b2 = ta * AT + tc;
+      nP[s] = (!skip && a < nvir && b < nvir) ? bkj[(int64_t)a * ld + b] : 0.0;
+      nQ[s] = (!skip && ta != tb && a2 < nvir && b2 < nvir) ? bkj[(int64_t)a2 * ld + b2] : 0.0;
     }
+  };
+  int ta = 0, tb = 0;
+  tile_pair_at(q0, nt, ta, tb);
+  if (q0 < q1) fetch(ta, tb);
+  for (int q = q0; q < q1; ++q) {
+    double vP[4], vQ[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { vP[s] = nP[s]; vQ[s] = nQ[s]; }
+    const int cta = ta, ctb = tb;
+    const bool diag = (cta == ctb);
+    tile_pair_next(nt, ta, tb);
+    if (q + 1 < q1) fetch(ta, tb);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      VP[r][tc] = vP[s];
+      VQ[r][tc] = vQ[s];
+    }
+    lds_barrier();
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      const int a = cta * AT + r, b = ctb * AT + tc;
+      if (a < nvir && b < nvir) put(a, b, vP[s], diag ? VP[tc][r] : VQ[tc][r]);
+      const int a2 = ctb * AT + r, b2 = cta * AT + tc;
+      if (!diag && a2 < nvir && b2 < nvir) put(a2, b2, vQ[s], VP[tc][r]);
+    }
+    lds_barrier();
   }
-  double h, l;
-  fast_two_sum(sh, sl, h, l);
-  block_dd_reduce(h, l);
-  if (t == 0) {
-    e_pair[(int64_t)k * nocc + j] = h + l;
-    e_pair[(int64_t)j * nocc + k] = h + l;
-  }
+  put_pair_energy(sh, sl, e_pair, nocc, k, j, true, epart);
 }
 
 // Amplitude pass over one slab group.
 // V/X slab: element (kk, a, jj, b) at S[((kk*nvir + a)*ncols + jj)*nvir + b],
 // kk < g, jj < ncols, occupied pair (k, j) = (k0 + kk, j0 + jj).
-// One workgroup per pair.  sym = 1 (energy only, slab holding j >= k0 only):
-// pairs with j < k are left to their mirror and e_kj is written to both e_kj
-// and e_jk (e_ij = e_ji).  sym = 2 (whole slab, blocks j < k not computed):
-// pairs j < k are left to their mirror, pairs j > k form both blocks
-// (amplitude_mirror_block; with energy_only as sym = 1).  A screened pair (pair_skip) writes e = 0 (and, unless
-// energy_only, zero X and T) without reading V.  For each pair of 32x32
-// tiles (ta <= tb) of the nvir x nvir block it reads V at (a,b) and (b,a),
-// forms X = V / D with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b in that
-// order (so X^T uses D[b,a] rounded its own way), then T = 2X - X^T, writes
-// X over V and T to the T slab (unless energy_only), and accumulates
+// Each pair's nvir x nvir block is covered by W workgroups (w < W), each
+// taking a contiguous range of its 32 x 32 tile pairs (ta <= tb); with W > 1
+// the workgroups write (hi, lo) partial sums to epart[2 (p W + w)] for
+// pair_energy_reduce_kernel (p = kk * ncols + jj), else e_pair directly.
+// For each tile pair a workgroup reads V at (a,b) and (b,a), forms
+// X = V / D with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b in that order (so
+// X^T uses D[b,a] rounded its own way), then T = 2X - X^T, writes X over V
+// and T to the T slab (unless energy_only), and accumulates
 // e_kj = sum_ab T[a,b] V[a,b] with compensated per-thread sums and a fixed
-// reduction order.  pair_skip (may be null) zeroes skipped pairs.
+// reduction order.  The next tile pair's V is fetched before the current one
+// is processed.
+// sym = 1 (energy only, slab holding j >= k0 only): pairs with j < k are left
+// to their mirror and e_kj is written to both e_kj and e_jk (e_ij = e_ji).
+// sym = 2 (whole slab, blocks j < k not computed): pairs j < k are left to
+// their mirror, pairs j > k form both blocks (amplitude_mirror_block; with
+// energy_only as sym = 1).  A screened pair (pair_skip, may be null) writes
+// e = 0 (and, unless energy_only, zero X and T) without reading V.
 __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
                                                 int nvir, int k0, int j0, int ncols, int sym, int energy_only,
-                                                const uint8_t* pair_skip, double* e_pair, int kk, int jj) {
-  __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];
+                                                const uint8_t* pair_skip, double* e_pair, int kk, int jj, int w,
+                                                int W, double* epart_all) {
+  __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];   // also the mirror path's V tiles
   const int k = k0 + kk, j = j0 + jj;
   if (sym && j < k) return;
+  double* epart = (W > 1) ? epart_all + 2 * (((int64_t)kk * ncols + jj) * W + w) : nullptr;
   const int64_t ld = (int64_t)ncols * nvir;
   double* blk = S + ((int64_t)kk * nvir * ncols + jj) * nvir;  // element (a,b) at blk[a*ld + b]
   double* tblk = Tslab + ((int64_t)kk * nvir * ncols + jj) * nvir;
   const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
+  const int nt = (nvir + AT - 1) / AT, npt = nt * (nt + 1) / 2;
+  const int q0 = (int)((int64_t)npt * w / W), q1 = (int)((int64_t)npt * (w + 1) / W);
   if (sym == 2 && !energy_only && j > k) {
-    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k, j);
+    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k, j, q0, q1, epart, XP, XQ);
     return;
   }
   if (skip && energy_only) {
-    if (threadIdx.x == 0) {
-      e_pair[(int64_t)k * nocc + j] = 0.0;
-      if (sym) e_pair[(int64_t)j * nocc + k] = 0.0;
-    }
+    put_pair_energy(0.0, 0.0, e_pair, nocc, k, j, sym != 0, epart);
     return;
   }
   const double ekj = eo[k] + eo[j];
   const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;  // 8 rows x 32 cols per pass
-  const int nt = (nvir + AT - 1) / AT;
   double sh = 0.0, sl = 0.0;
-  for (int ta = 0; ta < nt; ++ta) {
-    for (int tb = ta; tb < nt; ++tb) {
-      const bool diag = (ta == tb);
-      double vP[4], vQ[4], xP[4], xQ[4];
+  double nP[4], nQ[4];
+  auto fetch = [&](int ta, int tb) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = tr0 + 8 * s;
-        const int a = ta * AT + r, b = tb * AT + tc;   // tile P element (a, b)
-        const int a2 = tb * AT + r, b2 = ta * AT + tc; // tile Q element (a2, b2)
-        double v = 0.0, x = 0.0;
-        if (a < nvir && b < nvir) {
-          v = skip ? 0.0 : blk[(int64_t)a * ld + b];
-          const double d = (ekj - ev[a]) - ev[b];
-          x = v / d;
-        }
-        vP[s] = v; xP[s] = x; XP[r][tc] = x;
-        v = 0.0; x = 0.0;
-        if (!diag && a2 < nvir && b2 < nvir) {
-          v = skip ? 0.0 : blk[(int64_t)a2 * ld + b2];
-          const double d = (ekj - ev[a2]) - ev[b2];
-          x = v / d;
-        }
-        vQ[s] = v; xQ[s] = x; XQ[r][tc] = x;
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      const int a = ta * AT + r, b = tb * AT + tc;   // tile P element (a, b)
+      const int a2 = tb * AT + r, b2 = ta * AT + tc; // tile Q element (a2, b2)
+      nP[s] = (!skip && a < nvir && b < nvir) ? blk[(int64_t)a * ld + b] : 0.0;
+      nQ[s] = (!skip && ta != tb && a2 < nvir && b2 < nvir) ? blk[(int64_t)a2 * ld + b2] : 0.0;
+    }
+  };
+  int ta = 0, tb = 0;
+  tile_pair_at(q0, nt, ta, tb);
+  if (q0 < q1) fetch(ta, tb);
+  for (int q = q0; q < q1; ++q) {
+    const int cta = ta, ctb = tb;
+    const bool diag = (cta == ctb);
+    double vP[4], vQ[4], xP[4], xQ[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { vP[s] = nP[s]; vQ[s] = nQ[s]; }
+    tile_pair_next(nt, ta, tb);
+    if (q + 1 < q1) fetch(ta, tb);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      const int a = cta * AT + r, b = ctb * AT + tc;
+      const int a2 = ctb * AT + r, b2 = cta * AT + tc;
+      double x = 0.0;
+      if (a < nvir && b < nvir) x = vP[s] / ((ekj - ev[a]) - ev[b]);
+      xP[s] = x; XP[r][tc] = x;
+      x = 0.0;
+      if (!diag && a2 < nvir && b2 < nvir) x = vQ[s] / ((ekj - ev[a2]) - ev[b2]);
+      xQ[s] = x; XQ[r][tc] = x;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = tr0 + 8 * s;
+      const int a = cta * AT + r, b = ctb * AT + tc;
+      const double xt = diag ? XP[tc][r] : XQ[tc][r];   // X[b, a]
+      const double tv = 2.0 * xP[s] - xt;
+      if (a < nvir && b < nvir) {
+        double p = tv * vP[s], e;
+        two_sum(sh, p, sh, e);
+        sl += e;
+        if (!energy_only) { blk[(int64_t)a * ld + b] = xP[s]; tblk[(int64_t)a * ld + b] = tv; }
       }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int r = tr0 + 8 * s;
-        const int a = ta * AT + r, b = tb * AT + tc;
-        const double xt = diag ? XP[tc][r] : XQ[tc][r];   // X[b, a]
-        const double tv = 2.0 * xP[s] - xt;
-        if (a < nvir && b < nvir) {
-          double p = tv * vP[s], e;
+      if (!diag) {
+        const int a2 = ctb * AT + r, b2 = cta * AT + tc;
+        const double xt2 = XP[tc][r];
+        const double tv2 = 2.0 * xQ[s] - xt2;
+        if (a2 < nvir && b2 < nvir) {
+          double p = tv2 * vQ[s], e;
           two_sum(sh, p, sh, e);
           sl += e;
-          if (!energy_only) { blk[(int64_t)a * ld + b] = xP[s]; tblk[(int64_t)a * ld + b] = tv; }
-        }
-        if (!diag) {
-          const int a2 = tb * AT + r, b2 = ta * AT + tc;
-          const double xt2 = XP[tc][r];
-          const double tv2 = 2.0 * xQ[s] - xt2;
-          if (a2 < nvir && b2 < nvir) {
-            double p = tv2 * vQ[s], e;
-            two_sum(sh, p, sh, e);
-            sl += e;
-            if (!energy_only) { blk[(int64_t)a2 * ld + b2] = xQ[s]; tblk[(int64_t)a2 * ld + b2] = tv2; }
-          }
+          if (!energy_only) { blk[(int64_t)a2 * ld + b2] = xQ[s]; tblk[(int64_t)a2 * ld + b2] = tv2; }
         }
       }
-      __syncthreads();
     }
+    lds_barrier();
   }
-  double h, l;
-  fast_two_sum(sh, sl, h, l);
-  block_dd_reduce(h, l);
-  if (t == 0) {
-    e_pair[(int64_t)k * nocc + j] = h + l;
-    if (sym) e_pair[(int64_t)j * nocc + k] = h + l;
-  }
+  put_pair_energy(sh, sl, e_pair, nocc, k, j, sym != 0, epart);
 }
 
+// One workgroup per (pair, w): blockIdx.x = (kk * ncols + jj) * W + w.
 __global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
                                                         int nocc, int nvir, int k0, int j0, int ncols, int sym,
                                                         int energy_only, const uint8_t* pair_skip, double* e_pair,
-                                                        const int32_t* status) {
+                                                        int W, double* epart, const int32_t* status) {
   if (*status != 0) return;
-  const int kk = blockIdx.x / ncols, jj = blockIdx.x - kk * ncols;
-  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, j0, ncols, sym, energy_only, pair_skip, e_pair, kk, jj);
+  const int p = blockIdx.x / W, w = blockIdx.x - p * W;
+  const int kk = p / ncols, jj = p - kk * ncols;
+  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, j0, ncols, sym, energy_only, pair_skip, e_pair, kk, jj, w, W,
+                  epart);
+}
+
+// e_kj from the W partial sums of each pair of a slab group (double-double,
+// added in order w = 0, 1, ...); with sym also e_jk.  One thread per pair.
+__global__ __launch_bounds__(256) void pair_energy_reduce_kernel(const double* epart, int W, int nocc, int k0, int j0,
+                                                                 int g, int ncols, int sym, double* e_pair,
+                                                                 const int32_t* status) {
+  if (*status != 0) return;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)g * ncols) return;
+  const int kk = (int)(p / ncols), jj = (int)(p - (int64_t)kk * ncols);
+  const int k = k0 + kk, j = j0 + jj;
+  if (sym && j < k) return;
+  double h = 0.0, l = 0.0;
+  for (int w = 0; w < W; ++w) dd_add(h, l, epart[2 * (p * W + w)], epart[2 * (p * W + w) + 1]);
+  e_pair[(int64_t)k * nocc + j] = h + l;
+  if (sym) e_pair[(int64_t)j * nocc + k] = h + l;
 }
 
 // out[m*ldo + n] = (accumulate ? out : 0) + alpha * sum_{z < splits} W[z*zs + m*ldw + n],

@@ -145,10 +145,23 @@ struct Plan {
   size_t off_dbv, off_ev, off_dbg, off_eg, off_cmax, off_dt, off_et;
   int64_t g;                 // occupied orbitals per slab group
   int64_t s_ab, s_ij, s_gam; // split-K factors
-  size_t off_status, off_V, off_T, off_e, off_pab, off_pij, off_gam, total;
+  size_t off_status, off_V, off_T, off_e, off_pab, off_pij, off_gam, off_epart, total;
 };
 
-int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density, const rimp2_opts* o, Plan* p) {
+// Workgroups per pair block of an amplitude launch over `pairs` pair blocks
+// of nvir x nvir: enough for about 8 waves of the resident workgroups, at
+// most kAmpSplitMax and at most one per tile pair.
+constexpr int64_t kAmpSplitMax = 64;
+int64_t amp_splits(int64_t pairs, int64_t nvir) {
+  const int64_t nt = (nvir + 31) / 32, npt = nt * (nt + 1) / 2;
+  const int64_t w = (6144 + pairs - 1) / pairs;
+  return std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(w, kAmpSplitMax), npt));
+}
+
+// grouped: the fragment runs in a batch wave (whole slab, no split amplitude
+// partials).
+int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density, const rimp2_opts* o, Plan* p,
+              bool grouped = false) {
   if (nocc < 1 || nvir < 1 || naux < 1 || nocc > (1 << 20) || nvir > (1 << 24) || naux > (1 << 24))
     return fail(RIMP2_EINVAL, "sizes must be >= 1 (nocc=%lld nvir=%lld naux=%lld)", (long long)nocc,
                 (long long)nvir, (long long)naux);
@@ -189,6 +202,17 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->off_pab = off; if (density) off = align_up(off + 8 * (size_t)p->s_ab * nvir * nvir);
   p->off_pij = off; if (density) off = align_up(off + 8 * (size_t)p->s_ij * nocc * nocc);
   p->off_gam = off; if (gamma && p->s_gam > 1 && !p->split) off = align_up(off + 8 * (size_t)p->s_gam * g * nvir * naux);
+  p->off_epart = off;
+  if (!grouped) {  // largest partial array of the amplitude launches (see run_fragment)
+    const bool eonly = !(gamma || density);
+    int64_t most = 0;
+    for (int64_t k0 = 0; k0 < nocc; k0 += g) {
+      const int64_t pairs = std::min<int64_t>(g, nocc - k0) * (eonly ? nocc - k0 : nocc);
+      const int64_t W = amp_splits(pairs, nvir);
+      if (W > 1) most = std::max(most, pairs * W);
+    }
+    off = align_up(off + 16 * (size_t)most);
+  }
   p->off_dbv = p->off_ev = p->off_dbg = p->off_eg = p->off_cmax = p->off_dt = p->off_et = off;
   if (p->split) {
     const int64_t L = nocc * nvir;
@@ -204,7 +228,6 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   }
   p->total = off;
   int rc;
-  if ((rc = check_grid(g * nocc, "amplitude"))) return rc;
   if (gamma && p->s_gam > 1 && (rc = check_grid(cdiv(g * nvir * naux, 256), "reduction"))) return rc;
   if (p->split && ((rc = check_grid(nocc * nvir, "digit split")) || (rc = check_grid(cdiv(p->kpg, 32), "digit split"))))
     return rc;
@@ -571,12 +594,22 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         return rc;
       }
     }
-    if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
-           hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols)), dim3(256), 0, st, V, T, eo, ev,
-                              (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, energy_only ? 1 : (mirror ? 2 : 0),
-                              energy_only ? 1 : 0, skip, ep, status);
-         })))
-      return rc;
+    {
+      const int64_t W = amp_splits(gc * ncols, nvir);
+      double* epart = (double*)(ws + P.off_epart);
+      const int sym = energy_only ? 1 : (mirror ? 2 : 0);
+      if ((rc = check_grid(gc * ncols * W, "amplitude"))) return rc;
+      if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
+             hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols * W)), dim3(256), 0, st, V, T, eo, ev,
+                                (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, sym, energy_only ? 1 : 0, skip,
+                                ep, (int)W, epart, status);
+             if (W > 1)
+               hipLaunchKernelGGL(pair_energy_reduce_kernel, dim3((unsigned)cdiv(gc * ncols, 256)), dim3(256), 0, st,
+                                  (const double*)epart, (int)W, (int)nocc, (int)k0, (int)j0, (int)gc, (int)ncols, sym,
+                                  ep, status);
+           })))
+        return rc;
+    }
     if (P.gamma) {
       GemmParams gp{};
       gp.M = gc * nvir; gp.N = naux; gp.K = L;
@@ -750,7 +783,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     rimp2_opts o{};
     o.slab_group = d[f].nocc;     // whole slab
     Plan P;
-    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, &o, &P)))
+    if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, &o, &P, true)))
       return fail(rc, "fragment %d: %s", f, g_err);
     P.s_gam = 1;
     if (P.total > budget) {
