@@ -482,7 +482,7 @@ void launch_split_cols(const double* X, int64_t K, int64_t N, int64_t ld, const 
 template <int S>
 void launch_oz8(OzParams op, hipStream_t st) {
   const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
-  hipLaunchKernelGGL(gemm_oz8_kernel<S>, dim3((unsigned)nwg), dim3(256), 0, st, op);
+  hipLaunchKernelGGL((gemm_oz8_kernel<S, (S >= 6) ? 1 : 2>), dim3((unsigned)nwg), dim3(256), 0, st, op);
 }
 #define RIMP2_SWITCH_S(S, CALL)                                   \
   switch (S) {                                                    \

@@ -121,16 +121,21 @@ struct OzParams {
 };
 
 // 256 threads = 4 waves in 2 x 2; workgroup tile 64 x 64, wave tile 32 x 32
-// (2 x 2 MFMA blocks); all S digit slices of a 64-wide reduction step staged
-// in LDS (double buffered, 80-byte row pitch: conflict-free 16-byte reads).
-template <int S>
-__global__ __launch_bounds__(256, 1) void gemm_oz8_kernel(OzParams p) {
+// (2 x 2 MFMA blocks).  All S digit slices of a 64-wide reduction step are
+// moved global -> LDS by global_load_lds_dwordx4 (no register staging): wave w
+// moves row block w (16 rows x 64 bytes, 1 KB) of every (slice, operand).
+// Within a 1 KB block lane l writes bytes [16 l, 16 l + 16), and it loads row
+// r = l / 4, 16-byte chunk (l % 4) ^ ((r / 4) % 4): an XOR swizzle that makes
+// the MFMA fragment reads (16 lanes reading 16 rows of one chunk) free of
+// bank conflicts.  NBUF = 2 double-buffers the stage (the next step's copy
+// runs under this step's MFMAs); NBUF = 1 halves the LDS so that two
+// workgroups share a CU, which pays for S >= 6 (stage = S * 8 KB).
+template <int S, int NBUF>
+__global__ __launch_bounds__(256, 2) void gemm_oz8_kernel(OzParams p) {
   if (p.status != nullptr && *p.status != 0) return;
-  constexpr int TM = 64, TN = 64, PITCH = 80, ROWS = TM + TN;
-  constexpr int STAGE = S * ROWS * PITCH;                     // bytes per stage
-  constexpr int NLOAD = S * ROWS * 4;                         // 16-byte pieces per stage
-  constexpr int PER = (NLOAD + 255) / 256;
-  __shared__ __attribute__((aligned(16))) int8_t lds[2][STAGE];
+  constexpr int TM = 64, TN = 64;
+  constexpr int STAGE = S * 2 * 4 * 1024;      // S slices x (A, B) x 4 row blocks x 1 KB
+  __shared__ __attribute__((aligned(1024))) int8_t lds[NBUF][STAGE];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, l16 = lane & 15;
   const int wm = wv >> 1, wn = wv & 1;
@@ -139,35 +144,22 @@ __global__ __launch_bounds__(256, 1) void gemm_oz8_kernel(OzParams p) {
   const int gm = min(p.group_m, p.tiles_m - first_m), tin = wl - grp * gsz;
   const int64_t m0 = (int64_t)(first_m + tin % gm) * TM, n0 = (int64_t)(tin / gm) * TN;
 
-  // loader: piece q -> (slice s, tile row r, 16-byte column c)
-  const int8_t* src[PER];
-  int dst[PER];
+  // copy: rows past the end read the last row (their outputs are not stored)
+  const int dr = lane >> 2, dc = (lane & 3) ^ ((dr >> 2) & 3);
+  const int64_t rowA = p.a_row0 + min(m0 + 16 * wv + dr, p.M - 1), rowB = min(n0 + 16 * wv + dr, p.N - 1);
+  const int8_t* srcA = p.A + rowA * p.kp + 16 * dc;
+  const int8_t* srcB = p.B + rowB * p.kp + 16 * dc;
+  auto copy = [&](int buf, int64_t k) {
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int q = tid + 256 * u;
-    const int s = q / (ROWS * 4), rem = q - s * ROWS * 4, r = rem >> 2, c = rem & 3;
-    if (q < NLOAD) {
-      const int8_t* base;
-      if (r < TM) base = p.A + s * p.a_slice + (p.a_row0 + min(m0 + r, p.M - 1)) * p.kp;
-      else base = p.B + s * p.b_slice + min(n0 + (r - TM), p.N - 1) * p.kp;
-      src[u] = base + 16 * c;
-      dst[u] = (s * ROWS + r) * PITCH + 16 * c;
-    } else {
-      src[u] = nullptr;
-      dst[u] = -1;
+    for (int s = 0; s < S; ++s) {
+      __builtin_amdgcn_global_load_lds((const void*)(srcA + s * p.a_slice + k),
+                                       (void*)(lds[buf] + ((s * 2 + 0) * 4 + wv) * 1024), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(srcB + s * p.b_slice + k),
+                                       (void*)(lds[buf] + ((s * 2 + 1) * 4 + wv) * 1024), 16, 0, 0);
     }
-  }
-  v4i reg[PER];
-  auto gload = [&](int64_t k) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u)
-      if (dst[u] >= 0) reg[u] = *(const v4i*)(src[u] + k);
   };
-  auto sstore = [&](int b) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u)
-      if (dst[u] >= 0) *(v4i*)(lds[b] + dst[u]) = reg[u];
-  };
+  // fragment of lane (g, l16): row l16 of a row block, data chunk g
+  const int fpos = (l16 * 4 + (g ^ ((l16 >> 2) & 3))) * 16;
 
   v4i acc[S][2][2];
   double out[2][2][4];
@@ -203,35 +195,38 @@ __global__ __launch_bounds__(256, 1) void gemm_oz8_kernel(OzParams p) {
 
   const int nsteps = (int)(p.kp / 64);
   const int flush_every = (int)(kFlushK / 64);
-  if (nsteps > 0) {
-    gload(0);
-    sstore(0);
+  if (nsteps > 0) copy(0, 0);
+  for (int st = 0; st < nsteps; ++st) {
+    const int b = (NBUF == 2) ? (st & 1) : 0;
+    // LDS copies count in vmcnt: wait for this wave's, then the barrier makes
+    // every wave's visible (and frees the other buffer)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int st = 0; st < nsteps; ++st) {
-      const int b = st & 1;
-      if (st + 1 < nsteps) gload((int64_t)(st + 1) * 64);
-      const int8_t* L0 = lds[b];
-      v4i fa[S][2], fb[S][2];
+    if (NBUF == 2 && st + 1 < nsteps) copy(b ^ 1, (int64_t)(st + 1) * 64);
+    const int8_t* L0 = lds[b];
+    v4i fb[S][2];
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+    for (int t = 0; t < S; ++t)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          fa[s][i] = *(const v4i*)(L0 + (s * ROWS + wm * 32 + 16 * i + l16) * PITCH + 16 * g);
-          fb[s][i] = *(const v4i*)(L0 + (s * ROWS + TM + wn * 32 + 16 * i + l16) * PITCH + 16 * g);
-        }
+      for (int j = 0; j < 2; ++j) fb[t][j] = *(const v4i*)(L0 + ((t * 2 + 1) * 4 + 2 * wn + j) * 1024 + fpos);
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+    for (int s = 0; s < S; ++s) {
+      v4i fa[2];
 #pragma unroll
-        for (int t = 0; t < S - s; ++t)
+      for (int i = 0; i < 2; ++i) fa[i] = *(const v4i*)(L0 + ((s * 2 + 0) * 4 + 2 * wm + i) * 1024 + fpos);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+      for (int t = 0; t < S - s; ++t)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-              acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
-      if (st + 1 < nsteps) sstore(b ^ 1);
-      if ((st + 1) % flush_every == 0) flush();
-      __syncthreads();
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[t][j], acc[s + t][i][j], 0, 0, 0);
     }
+    if (NBUF == 1 && st + 1 < nsteps) {
+      __syncthreads();   // every wave is done reading the stage
+      copy(0, (int64_t)(st + 1) * 64);
+    }
+    if ((st + 1) % flush_every == 0) flush();
   }
   flush();
 #pragma unroll
