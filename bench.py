@@ -17,7 +17,6 @@ every input already resident in HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,12 +32,8 @@ METRIC = "RI-MP2 E+Γ TFLOP/s & %peak; split-prec/batched vs FP64 speedup at |Δ
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2410_21888_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as f:
-            h.update(fn.encode() + f.read())
-    return h.hexdigest()[:16]
+    from paper_2410_21888_amd.profsum import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(role: str, workload: str):

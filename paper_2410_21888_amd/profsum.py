@@ -1,0 +1,168 @@
+"""Summaries of rocprofv3 output for the library's kernels (measurement
+tooling; no part of the compute path).
+
+    python -m paper_2410_21888_amd.profsum trace <kernel_stats.csv>
+        per-kernel totals of a `rocprofv3 --kernel-trace --stats
+        --output-format csv` run, with each kernel's role
+
+    python -m paper_2410_21888_amd.profsum traffic <fetch.csv> <write.csv> \\
+            --workload large --json profiles/hbm_traffic.json
+        HBM bytes per launch and role from two `rocprofv3 --pmc FETCH_SIZE` /
+        `--pmc WRITE_SIZE` runs (counter_collection.csv), each counter scaled
+        by what it read for the largest runtime copy kernel of the run (the
+        1 GiB device-to-device copy `bench.py --calib-copy` makes), and tagged
+        with the hash of the kernel sources it was measured on
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+CALIB_BYTES = 1 << 30        # bench.py --calib-copy moves 1 GiB each way
+
+_GEMM_ROLES = {"0": "ints_gemm", "1": "gamma_gemm", "2": "pab_gemm", "3": "pij_gemm"}
+
+
+def kernel_source_hash() -> str:
+    """Hash of every file under csrc/ (names and contents)."""
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def role_of(name: str) -> str:
+    """The library role of a kernel symbol (the names rimp2_timing_collect uses)."""
+    m = re.search(r"gemm_f64_(?:kernel|grouped)<\s*\d+,\s*\d+,\s*\d+,\s*(?:true|false),\s*(\d)", name)
+    if m:
+        return _GEMM_ROLES[m.group(1)]
+    for key, role in (("gemm_oz8_kernel<", None), ("amplitude", "amplitude"),
+                      ("pair_energy_reduce", "amplitude (pair energy reduce)"),
+                      ("splitk_reduce", "splitk_reduce"), ("reduce_grouped", "splitk_reduce"),
+                      ("energy_sum", "energy_sum"), ("gap_check", "gap_check"), ("split_rows", "digit_split"),
+                      ("split_cols", "digit_split"), ("colmax", "digit_split"), ("zero_u64", "digit_split"),
+                      ("copy_status", "status_copy"), ("status_copy", "status_copy"),
+                      ("relocate_tables", "status_copy"), ("zero_counters", "status_copy"),
+                      (COPY_KERNEL, "(runtime copy)"), ("at::native", "(torch)"), ("three_index", "(input generator)")):
+        if key in name:
+            if role is None:
+                return "oz8"
+            return role
+    return "(other)"
+
+
+def _num(x: str) -> float:
+    return float(x) if x not in ("", None) else 0.0
+
+
+def _col(r: dict, *names) -> float:
+    for n in names:
+        if n in r:
+            return _num(r[n])
+    return 0.0
+
+
+def trace_summary(stats_csv: str) -> str:
+    """Markdown table of a kernel statistics CSV (rocprofv3 --stats, or
+    rocpd2summary's kernels summary)."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot_of = lambda r: _col(r, "TotalDurationNs", "Duration (Nsec)")
+    total = sum(tot_of(r) for r in rows) or 1.0
+    out = ["| role | kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -tot_of(r)):
+        name = r["Name"]
+        tot = tot_of(r)
+        calls = int(_col(r, "Calls"))
+        avg = _col(r, "AverageNs", "Average (Nsec)")
+        short = name if len(name) <= 70 else name[:70]
+        out.append("| %s | `%s` | %d | %.1f | %.3f | %.2f |" % (role_of(name), short, calls, tot / 1e6, avg / 1e6,
+                                                              100.0 * tot / total))
+    return "\n".join(out)
+
+
+def _per_kernel(counter_csv: str, counter: str):
+    """{dispatch id: (kernel name, value)} for one counter (values summed over
+    dimensions of the same dispatch)."""
+    d = {}
+    for r in csv.DictReader(open(counter_csv)):
+        if r["Counter_Name"] != counter:
+            continue
+        key = r["Dispatch_Id"]
+        name, v = d.get(key, (r["Kernel_Name"], 0.0))
+        d[key] = (name, v + _num(r["Counter_Value"]))
+    return d
+
+
+def traffic(fetch_csv: str, write_csv: str):
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    # calibration: the largest runtime copy of each run moved CALIB_BYTES each way
+    f_copy = max((v for n, v in fetch.values() if COPY_KERNEL in n), default=0.0)
+    w_copy = max((v for n, v in write.values() if COPY_KERNEL in n), default=0.0)
+    if f_copy <= 0 or w_copy <= 0:
+        raise SystemExit("no calibration copy found (run bench.py with --calib-copy)")
+    fs, ws = CALIB_BYTES / (f_copy * 1024.0), CALIB_BYTES / (w_copy * 1024.0)
+    acc = defaultdict(lambda: [0, 0.0, 0.0])
+    for vals, idx in ((fetch, 1), (write, 2)):
+        for name, v in vals.values():
+            role = role_of(name)
+            if role.startswith("("):
+                continue
+            acc[role][idx] += v
+    n_f = defaultdict(int)
+    for name, _ in fetch.values():
+        n_f[role_of(name)] += 1
+    out = {}
+    for role, (_, f_kib, w_kib) in acc.items():
+        n = n_f[role] or 1
+        out[role] = {"launches": n, "fetch_kib_raw": f_kib / n, "write_kib_raw": w_kib / n,
+                     "bytes_per_launch": (f_kib * fs + w_kib * ws) * 1024.0 / n}
+    return out, {"fetch_scale": fs, "write_scale": ws, "fetch_copy_kib": f_copy, "write_copy_kib": w_copy}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2410_21888_amd.profsum")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("stats_csv")
+    h = sub.add_parser("traffic")
+    h.add_argument("fetch_csv")
+    h.add_argument("write_csv")
+    h.add_argument("--workload", required=True)
+    h.add_argument("--json", help="merge the result into this JSON file")
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print("Kernel sources hash: %s\n" % kernel_source_hash())
+        print(trace_summary(a.stats_csv))
+        return 0
+    roles, cal = traffic(a.fetch_csv, a.write_csv)
+    src = kernel_source_hash()
+    print("Calibration: FETCH_SIZE x%.4f, WRITE_SIZE x%.4f (copy read %.0f / %.0f KiB for 1 GiB)\n" % (
+        cal["fetch_scale"], cal["write_scale"], cal["fetch_copy_kib"], cal["write_copy_kib"]))
+    print("Kernel sources hash: %s\n" % src)
+    print("| role | launches | FETCH_SIZE KiB/launch (raw) | WRITE_SIZE KiB/launch (raw) | HBM bytes/launch (scaled) |")
+    print("|---|---|---|---|---|")
+    for role, e in sorted(roles.items(), key=lambda kv: -kv[1]["bytes_per_launch"] * kv[1]["launches"]):
+        print("| %s | %d | %.4g | %.4g | %.4g |" % (role, e["launches"], e["fetch_kib_raw"], e["write_kib_raw"],
+                                                    e["bytes_per_launch"]))
+    if a.json:
+        d = json.load(open(a.json)) if os.path.exists(a.json) else {}
+        d[a.workload] = {r: dict(e, source_hash=src) for r, e in roles.items()}
+        d["calibration"] = cal
+        with open(a.json, "w") as f:
+            json.dump(d, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
