@@ -14,8 +14,12 @@
  *   P_ij = -sum_kab T_ik^ab X_jk^ab                      (Appendix, D^MP2_ij)
  *   P_ab =  sum_ijc T_ij^ac X_ij^bc                      (Appendix, D^MP2_ab)
  *
- * All arithmetic is IEEE FP64.  Results are deterministic: the same inputs on
- * the same GPU give bitwise identical outputs (no floating-point atomics).
+ * All arithmetic is IEEE FP64 unless opts->precision selects split products
+ * (rimp2_precision).  P_ij and P_ab are formed from their upper triangles and
+ * are exactly symmetric.  Results are deterministic: the same inputs and
+ * options on the same GPU give bitwise identical outputs (no floating-point
+ * atomics; the in-situ autotuner changes tile shapes only, never a summation
+ * order).
  *
  * Conventions for every entry point:
  *  - Pointers marked "device" are HIP device pointers; the caller owns every
@@ -162,7 +166,9 @@ typedef struct {
  * persistent launches whose workgroups take (fragment, tile) items from a
  * counter, largest fragment first).  Larger fragments run alone, as
  * rimp2_fragment does.  Only FP64 is supported (opts->precision must be
- * RIMP2_FP64; pair_skip must be NULL).
+ * RIMP2_FP64; pair_skip must be NULL).  With opts->autotune the grouped GEMM
+ * launches and the fragments that run alone are tuned in situ (see
+ * rimp2_autotune_report).
  *
  *   descs    HOST array of nfrag descriptors; the handle keeps a copy, and the
  *            device buffers they name must stay valid while the handle is used
