@@ -1,0 +1,45 @@
+"""The rocprofv3 summary tool on small synthetic counter files (CPU only)."""
+import csv
+import json
+
+from paper_2410_21888_amd import profsum
+
+HEAD = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size", "Kernel_Id",
+        "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
+        "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+INTS = "void rimp2::gemm_f64_kernel<128, 128, 16, false, 0, true, false>(rimp2::GemmParams)"
+GAMMA = "void rimp2::gemm_f64_kernel<128, 128, 16, true, 1, true, false>(rimp2::GemmParams)"
+
+
+def write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HEAD)
+        for i, (name, value) in enumerate(rows):
+            w.writerow([i, i, "Agent 1", 1, 1, 1, 256, 1, name, 256, 0, 0, 64, 0, 32, counter, value, 0, 1])
+
+
+def test_roles_of_kernel_symbols():
+    assert profsum.role_of(INTS) == "ints_gemm"
+    assert profsum.role_of(GAMMA) == "gamma_gemm"
+    assert profsum.role_of("void rimp2::gemm_f64_grouped<64, 64, 16, false, 3, true, true>(rimp2::GemmGroup)") == "pij_gemm"
+    assert profsum.role_of("rimp2::amplitude_kernel(double*, ...)") == "amplitude"
+    assert profsum.role_of("__amd_rocclr_copyBuffer") == "(runtime copy)"
+
+
+def test_traffic_scales_by_the_calibration_copy(tmp_path):
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    # the 1 GiB copy: FETCH_SIZE counts half of the bytes it moved, WRITE_SIZE all of them
+    write_counters(f, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 524288.0), (INTS, 1000.0), (INTS, 3000.0),
+                                     (GAMMA, 10.0)])
+    write_counters(w, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 1048576.0), (INTS, 100.0), (INTS, 300.0),
+                                     (GAMMA, 1.0)])
+    roles, cal = profsum.traffic(str(f), str(w))
+    assert abs(cal["fetch_scale"] - 2.0) < 1e-12 and abs(cal["write_scale"] - 1.0) < 1e-12
+    assert roles["ints_gemm"]["launches"] == 2
+    assert abs(roles["ints_gemm"]["bytes_per_launch"] - (2000.0 * 2 + 200.0) * 1024) < 1e-6
+    assert abs(roles["gamma_gemm"]["bytes_per_launch"] - (10.0 * 2 + 1.0) * 1024) < 1e-6
+    out = tmp_path / "t.json"
+    assert profsum.main(["traffic", str(f), str(w), "--workload", "w", "--json", str(out)]) == 0
+    d = json.load(open(out))
+    assert d["w"]["ints_gemm"]["source_hash"] == profsum.kernel_source_hash()
