@@ -202,7 +202,7 @@ def main():
                    "outputs": "E, e_ij, Gamma, P_ij, P_ab", "flops_counted": "algorithmic E+Gamma+P_ab+P_ij",
                    "slab_group": args.slab_group or "auto", "autotune": bool(args.autotune)},
         "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4),
-        "tflops_executed": round(fl["executed"] / dt / 1e12, 4),
+        "tflops_executed": round(sum(s["exec_flops"] for s in stats) / (t1 - t0) / 1e12, 4),
         "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": round(achieved, 4),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                      "avg_launch_ms": round(avg_ms, 4), "launches": dom["launches"],

@@ -248,8 +248,9 @@ def fragment_batch(frags: Sequence[dict], *, status: Optional[torch.Tensor] = No
 
 def flops(nocc: int, nvir: int, naux: int, gamma: bool = True, density: bool = True) -> dict:
     """Algorithmic FLOP counts of the path (2 per multiply-add): (ia|jb) over
-    unordered pairs, Gamma, P_ab and P_ij; and the GEMM FLOPs the kernels
-    execute (the (ia|jb) slabs cover ordered pairs)."""
+    unordered pairs, Gamma, P_ab and P_ij; and the plain GEMM FLOPs with the
+    (ia|jb) slabs over ordered pairs (the kernels run less where tiles are
+    triangular or mirrored; rimp2_timing_collect reports what they execute)."""
     o, v, x = float(nocc), float(nvir), float(naux)
     alg = {"ints": o * (o + 1) * v * v * x}
     exe = {"ints": 2 * o * o * v * v * x}
