@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -327,6 +328,21 @@ def bench_mbe3(args, torch, synth, rm, dev):
     print("[bench] per-fragment loop %.3f s" % t_loop, file=sys.stderr, flush=True)
     E_loop = torch.stack([d["E"] for d in frags]).clone()
     dE = float((E_loop - E_batch).abs().max())
+    split = None
+    if args.precision == "split":   # every fragment alone, split products for (ia|jb) and Gamma
+        sb = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8))
+        ws_s = torch.empty(sb.workspace_bytes, dtype=torch.uint8, device=dev)
+        sb.run(ws_s, status)
+        torch.cuda.synchronize()
+        t_split = timed(lambda: sb.run(ws_s, status), args.steps)
+        E_s = torch.stack([d["E"] for d in frags])
+        dE_s = max(abs(math.fsum([float(a[0]), float(a[1]), -float(b[0]), -float(b[1])]))
+                   for a, b in zip(E_s.cpu().numpy(), E_batch.cpu().numpy()))
+        sb.close()
+        del ws_s
+        split = {"split_batch_tflops": round(total_alg / t_split / 1e12, 4),
+                 "speedup_split_vs_fp64_batch": round(t_batch / t_split, 4), "max_abs_dE_vs_fp64_Eh": dE_s}
+        print("[bench] split-precision batch %.3f s" % t_split, file=sys.stderr, flush=True)
     # in-situ tile autotuning: the first passes trial the candidates, later passes use the choices
     rm.autotune_reset()
     tb = rm.Batch(frags, opts=rm.make_opts(autotune=True))
@@ -391,6 +407,7 @@ def bench_mbe3(args, torch, synth, rm, dev):
                      "shapes": len(rep), "shapes_off_default": n_changed, "E_bitwise_equal_to_fixed": tuned_bitwise,
                      "chosen_tiles": decisions},
         "max_abs_dE_batch_vs_loop_Eh": dE,
+        "split": split,
         "roofline": {"bound": "mfma", "kernel": dom["name"] + " (grouped)", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None,
                      "note": "grouped launches mix fragments; per-launch algorithmic FLOPs are not split by role"},

@@ -767,8 +767,11 @@ size_t place(size_t& off, size_t bytes) {
 
 int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, rimp2_batch_s* B) {
   if (nfrag < 0 || (nfrag > 0 && !d)) return fail(RIMP2_EINVAL, "bad batch arguments");
-  if (opts && opts->precision != RIMP2_FP64) return fail(RIMP2_ENOTSUP, "batches run in FP64 only");
+  if (opts && opts->precision != RIMP2_FP64 && opts->precision != RIMP2_SPLIT_INT8)
+    return fail(RIMP2_ENOTSUP, "precision %d is not supported", opts->precision);
   if (opts && opts->pair_skip) return fail(RIMP2_ENOTSUP, "pair_skip is not supported for batches");
+  // split products have no grouped kernels: every fragment then runs alone
+  const bool all_solo = opts && opts->precision == RIMP2_SPLIT_INT8;
   B->d.assign(d, d + nfrag);
   B->autotune = opts && opts->autotune;
   B->plan.resize(nfrag);
@@ -786,7 +789,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, &o, &P, true)))
       return fail(rc, "fragment %d: %s", f, g_err);
     P.s_gam = 1;
-    if (P.total > budget) {
+    if (all_solo || P.total > budget) {
       solo[f] = 1;
       if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &P)))
         return fail(rc, "fragment %d: %s", f, g_err);

@@ -100,7 +100,9 @@ def test_batch_plan_errors_and_sizes():
         arr[i].B, arr[i].eps_occ, arr[i].eps_vir, arr[i].E = 256, 512, 768, 1024
     n = ctypes.c_size_t(0)
     assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_OK and n.value > 0
-    split = R.make_opts(precision=rm.SPLIT_INT8)
-    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(split), ctypes.byref(n)) == rm.RIMP2_ENOTSUP
+    split = R.make_opts(precision=rm.SPLIT_INT8)   # runs every fragment alone
+    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(split), ctypes.byref(n)) == rm.RIMP2_OK
+    bad = R.make_opts(precision=9)
+    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(bad), ctypes.byref(n)) == rm.RIMP2_ENOTSUP
     arr[1].nocc = 0
     assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_EINVAL

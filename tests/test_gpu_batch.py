@@ -140,3 +140,16 @@ def test_batch_autotune_bitwise_and_decides():
         assert e["best"] >= 0 and e["timed"] == [2, 2], e
     b.close()
     rm.autotune_reset()
+
+
+def test_batch_split_precision_matches_oracle():
+    frags, refs = make_frags(MBE_LIKE)
+    say("split-precision batch of %d fragments" % len(frags))
+    status = torch.full((len(frags),), 7, dtype=torch.int32, device="cuda:0")
+    rm.fragment_batch(frags, status=status, opts=rm.make_opts(precision=rm.SPLIT_INT8))
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(frags)
+    for d, ref in zip(frags, refs):
+        assert energy_error(d["E"], ref["E_hi"], ref["E_lo"]) <= 1e-6
+        for key in ("Gamma", "P_ij", "P_ab", "e_pair"):
+            assert rel_fro(d[key].cpu().numpy(), ref[key]) <= 1e-8, key
