@@ -47,7 +47,7 @@ def test_autotune_bitwise_and_decides():
                                                               e["timed"], ["%.3f" % t for t in e["min_ms"]]))
         assert e["best"] >= 0, e
         assert all(t == 2 for t in e["timed"]), e
-        assert all(ms > 0 for ms in e["min_ms"]), e
+        assert all(ms >= 0 for ms in e["min_ms"]), e
         assert e["uses"] >= 8
     rm.autotune_reset()
     assert rm.autotune_report() == []
