@@ -168,6 +168,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print("[bench] timed %d step(s) in %.3f s" % (args.steps, t1 - t0), file=sys.stderr, flush=True)
+    # adjacent step, outside the timed region: the metric contraction of Gamma
+    # with a synthetic symmetric J^{-1/2} stand-in
+    from paper_2410_21888_amd import gradient as GR
+    q = torch.arange(naux, dtype=torch.float64, device=dev)
+    Jm = torch.exp(-(q[:, None] - q[None, :]).abs() / 50.0) * 0.01 + torch.eye(naux, **f64)
+    Gm = torch.empty_like(G)
+    GR.gamma_metric(G, Jm, Gm)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    GR.gamma_metric(G, Jm, Gm)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - tg
+    del Gm, Jm
 
     fl = rm.flops(nocc, nvir, naux)
     dt = (t1 - t0) / args.steps
@@ -211,6 +224,8 @@ def main():
                      "traffic": traffic,
                      "executed_tflops": round(executed, 4), "frac_executed": round(executed / FP64_PEAK_TFLOPS, 4)},
         "E_hi": float(E[0]), "E_lo": float(E[1]),
+        "gamma_metric": {"ms": round(tg * 1e3, 3), "tflops": round(2.0 * nocc * nvir * naux * naux / tg / 1e12, 3),
+                         "note": "Gamma J^-1/2 with a synthetic metric, outside the timed step"},
     }
     if dom["name"] == "ints_gemm":
         out["roofline"]["note"] = ("the (ia|jb) GEMM computes ordered pairs (twice the symmetric algorithmic count) "

@@ -187,3 +187,10 @@ def p_ij_element(B, eps_occ, eps_vir, i: int, j: int):
         _, X, _ = pair_quantities(B, eps_occ, eps_vir, k, j)
         s = s + np.sum(T * X)
     return -s
+
+
+def gamma_metric(Gamma, Jm):
+    """The Appendix's Gamma^P_ia = sum_Q Gamma~^Q_ia J^{-1/2}_PQ, from the
+    fragment kernel's Gamma~ (taken before this contraction; see the module
+    header): out[i, a, P] = sum_Q Gamma[i, a, Q] Jm[P, Q]."""
+    return Gamma @ Jm.T

@@ -7,9 +7,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librimp2.so")
-SOURCES = [os.path.join(CSRC, "rimp2.hip"), os.path.join(CSRC, "screen.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("rimp2.hip", "screen.hip", "gradient.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + [
-    os.path.join(os.path.dirname(HERE), "include", f) for f in ("rimp2.h", "rimp2_screen.h")]
+    os.path.join(os.path.dirname(HERE), "include", f) for f in ("rimp2.h", "rimp2_screen.h", "rimp2_gradient.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

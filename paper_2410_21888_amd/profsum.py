@@ -32,10 +32,15 @@ CALIB_BYTES = 1 << 30        # bench.py --calib-copy moves 1 GiB each way
 _GEMM_ROLES = {"0": "ints_gemm", "1": "gamma_gemm", "2": "pab_gemm", "3": "pij_gemm"}
 
 
+# the sources the fragment path's kernels are built from (screening and the
+# adjacent gradient steps have their own files and do not enter it)
+FRAGMENT_SOURCES = ("batch.hpp", "common.hpp", "gemm_f64.hpp", "kernels.hpp", "rimp2.hip", "split_int8.hpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of every file under csrc/ (names and contents)."""
+    """Hash of the fragment path's kernel sources (names and contents)."""
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(CSRC)):
+    for fn in FRAGMENT_SOURCES:
         with open(os.path.join(CSRC, fn), "rb") as f:
             h.update(fn.encode() + f.read())
     return h.hexdigest()[:16]
@@ -43,9 +48,11 @@ def kernel_source_hash() -> str:
 
 def role_of(name: str) -> str:
     """The library role of a kernel symbol (the names rimp2_timing_collect uses)."""
-    m = re.search(r"gemm_f64_(?:kernel|grouped)<\s*\d+,\s*\d+,\s*\d+,\s*(?:true|false),\s*(\d)", name)
+    m = re.search(r"gemm_f64_(?:kernel|grouped)<\s*\d+,\s*\d+,\s*\d+,\s*(true|false),\s*(\d)", name)
     if m:
-        return _GEMM_ROLES[m.group(1)]
+        if m.group(2) == "1" and m.group(1) == "false":   # K-contiguous B: the metric contraction of Gamma
+            return "gamma_metric"
+        return _GEMM_ROLES[m.group(2)]
     for key, role in (("gemm_oz8_kernel<", None), ("amplitude", "amplitude"),
                       ("pair_energy_reduce", "amplitude (pair energy reduce)"),
                       ("splitk_reduce", "splitk_reduce"), ("reduce_grouped", "splitk_reduce"),

@@ -301,6 +301,24 @@ def pin_exact_sum(O):
     assert hi == 2.0 ** 60 and lo == 2.0
 
 
+def pin_gamma_metric_is_three_centre_derivative(O):
+    """With B = B3 M (B[..., P] = sum_Q B3[..., Q] M[Q, P]; in the paper M =
+    J^{-1/2} and B3 the three-centre integrals), the chain rule and
+    dE/dB = 4 Gamma give dE/dB3 = 4 gamma_metric(Gamma, M), by complex step
+    of the energy.  M is not symmetric, so a transposed metric fails."""
+    h = 1e-30
+    B3, eo, ev = tiny_inputs(2, 3, 4, 21)
+    M = np.random.default_rng(22).standard_normal((4, 4))
+    want = 4.0 * O.gamma_metric(O.fragment(B3 @ M, eo, ev, density=False)["Gamma"], M)
+    got = np.zeros_like(B3)
+    for idx in np.ndindex(B3.shape):
+        Bc = B3.astype(np.complex128)
+        Bc[idx] += 1j * h
+        got[idx] = _complex_E(O, Bc @ M, eo, ev).imag / h
+    assert rel(got, want) <= 1e-12, rel(got, want)
+
+
 ALL_PINS = [pin_brute_force, pin_closed_form_single_pair, pin_equal_energies, pin_dE_dB_is_4_gamma,
             pin_dE_deps_is_2_diagP, pin_symmetry_and_sign, pin_aux_rotation, pin_global_shift,
-            pin_scaling, pin_zero_padding, pin_permutation, pin_sampled_entry_points, pin_exact_sum]
+            pin_scaling, pin_zero_padding, pin_permutation, pin_sampled_entry_points, pin_exact_sum,
+            pin_gamma_metric_is_three_centre_derivative]

@@ -106,3 +106,13 @@ def test_batch_plan_errors_and_sizes():
     assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(bad), ctypes.byref(n)) == rm.RIMP2_ENOTSUP
     arr[1].nocc = 0
     assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_EINVAL
+
+
+def test_gamma_metric_host_errors():
+    from paper_2410_21888_amd import gradient as G
+    L = G._L()
+    assert L.rimp2_gamma_metric(0, 3, 4, 256, 512, 1024, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_gamma_metric(2, 3, 4, None, 512, 1024, None) == rm.RIMP2_EINVAL
+    # out overlapping Gamma
+    assert L.rimp2_gamma_metric(2, 3, 4, 4096, 512, 4096 + 8, None) == rm.RIMP2_EINVAL
+    assert b"overlap" in L.rimp2_last_error()

@@ -1,0 +1,44 @@
+"""Metric contraction of Gamma on the GPU (rimp2_gamma_metric) against the
+oracle, element by element; the metric is not symmetric, so a transposed
+operand would show."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rimp2_oracle as O
+import paper_2410_21888_amd as rm
+from paper_2410_21888_amd import gradient as G
+from gpu_util import to_dev, rel_fro, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 17, 33), (5, 40, 300), (4, 130, 257), (2, 64, 128)])
+def test_gamma_metric_matches_oracle(shape):
+    nocc, nvir, naux = shape
+    rng = np.random.default_rng(sum(shape))
+    Gam = rng.standard_normal((nocc, nvir, naux))
+    Jm = rng.standard_normal((naux, naux))
+    say("gamma_metric %s" % (shape,))
+    dG, dJ = to_dev(Gam, Jm)
+    got = G.gamma_metric(dG, dJ).cpu().numpy()
+    torch.cuda.synchronize()
+    assert rel_fro(got, O.gamma_metric(Gam, Jm)) <= 1e-13
+
+
+def test_gamma_metric_after_the_fragment_kernel():
+    f = synth.random_fragment(6, 50, 96, seed=41)
+    B, eo, ev = f.arrays()
+    Jm = np.random.default_rng(42).standard_normal((96, 96))
+    r = rm.fragment(*to_dev(B, eo, ev), density=False)
+    got = G.gamma_metric(r.Gamma, to_dev(Jm)[0]).cpu().numpy()
+    ref = O.gamma_metric(O.fragment(B, eo, ev, density=False)["Gamma"], Jm)
+    assert rel_fro(got, ref) <= 1e-13
+
+
+def test_gamma_metric_rejects_overlap():
+    g = torch.zeros((2, 3, 4), dtype=torch.float64, device="cuda:0")
+    j = torch.eye(4, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(rm.Rimp2Error):
+        G.gamma_metric(g, j, out=g)

@@ -42,6 +42,8 @@ MUTANTS = [
     ("gamma_row exchange from row", "T_row = 2.0 * row / D_row - col / D_row", "T_row = 2.0 * row / D_row - row / D_row"),
     ("p_ab_element wrong denominator", "X_b = Vb_row / D[b]", "X_b = Vb_row / D[a]"),
     ("p_ij_element sign", "    return -s\n", "    return s\n"),
+    ("gamma_metric transposed", "return Gamma @ Jm.T", "return Gamma @ Jm"),
+    ("gamma_metric drops the metric", "return Gamma @ Jm.T", "return Gamma"),
     ("pair_energy uses X", "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * V)",
      "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * X)"),
 ]

@@ -22,6 +22,7 @@ def write_counters(path, counter, rows):
 def test_roles_of_kernel_symbols():
     assert profsum.role_of(INTS) == "ints_gemm"
     assert profsum.role_of(GAMMA) == "gamma_gemm"
+    assert profsum.role_of(GAMMA.replace("true, 1", "false, 1")) == "gamma_metric"
     assert profsum.role_of("void rimp2::gemm_f64_grouped<64, 64, 16, false, 3, true, true>(rimp2::GemmGroup)") == "pij_gemm"
     assert profsum.role_of("rimp2::amplitude_kernel(double*, ...)") == "amplitude"
     assert profsum.role_of("__amd_rocclr_copyBuffer") == "(runtime copy)"
