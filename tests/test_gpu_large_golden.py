@@ -1,0 +1,61 @@
+"""The large fragment (nocc=200, nvir=1800, naux=6000) at full size, in the
+launch configuration bench.py times (default options: slab groups of 6
+occupied orbitals, every output), against the CPU oracle's stored outputs.
+
+tests/golden/large_oracle.npz was written by tests/golden/make_large_golden.py,
+which calls only oracle/ and synth/ (about 1.7 h on 6 cores).  Gamma is not
+stored; its rows are checked one by one with oracle.gamma_row.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rimp2_oracle as O
+import paper_2410_21888_amd as rm
+from gpu_util import rel_fro, say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_oracle.npz")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden file not generated")
+def test_large_fragment_against_stored_oracle():
+    g = np.load(GOLDEN)
+    f = synth.LARGE
+    assert tuple(g["shape"]) == (f.nocc, f.nvir, f.naux) and int(g["seed"]) == f.seed
+    assert float(g["decay"]) == f.decay
+    say("large golden: generating inputs")
+    B, eo, ev = f.arrays()
+    dev = torch.device("cuda:0")
+    dB = torch.from_numpy(B).to(dev)
+    deo, dev_ = torch.from_numpy(eo).to(dev), torch.from_numpy(ev).to(dev)
+    say("large golden: running the fragment kernel")
+    r = rm.fragment(dB, deo, dev_)
+    torch.cuda.synchronize()
+    E = r.E.cpu().numpy()
+    dE = abs(math.fsum([float(E[0]), float(E[1]), -float(g["E"][0]), -float(g["E"][1])]))
+    say("large golden: |dE| = %.3e Eh (E = %.6e)" % (dE, float(g["E"][0])))
+    assert dE <= 1e-6
+    ep = r.e_pair.cpu().numpy()
+    ref_ep = g["e_pair"]
+    assert np.all(np.abs(ep - ref_ep) <= 1e-12 * np.abs(ref_ep) + 1e-15)
+    pij = r.P_ij.cpu().numpy()
+    assert rel_fro(pij, g["P_ij"]) <= 1e-12
+    pab = r.P_ab.cpu().numpy()
+    rows = g["P_ab_row_index"]
+    assert rel_fro(pab[rows], g["P_ab_rows"]) <= 1e-12
+    assert rel_fro(np.diag(pab), g["P_ab_diag"]) <= 1e-12
+    assert abs(np.linalg.norm(pab) - float(g["P_ab_fro"])) <= 1e-12 * float(g["P_ab_fro"])
+    del dB
+    for i, a in ((0, 0), (57, 900), (120, 3), (199, 1799)):
+        got = r.Gamma[i, a].cpu().numpy()
+        ref = O.gamma_row(B, eo, ev, i, a)
+        err = rel_fro(got, ref)
+        say("large golden: Gamma[%d, %d, :] rel err %.2e" % (i, a, err))
+        assert err <= 1e-12
