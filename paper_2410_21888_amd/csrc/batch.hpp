@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256) void amplitude_grouped(const AmpDesc* descs, c
   if (*d.status != 0) return;
   const int64_t u = blockIdx.x - prefix[f];
   const int kk = (int)(u / d.nocc), j = (int)(u - (int64_t)kk * d.nocc);
-  amplitude_block(d.V, d.T, d.eo, d.ev, d.nocc, d.nvir, 0, 0, d.nocc, 2, d.energy_only, nullptr, d.e_pair, kk, j, 0, 1,
-                  nullptr);
+  amplitude_block(d.V, d.T, d.eo, d.ev, d.nocc, d.nvir, 0, 0, d.nocc, 2, d.nocc, d.energy_only, nullptr, d.e_pair, kk,
+                  j, 0, 1, nullptr);
 }
 
 // prefix counts 256-element blocks per problem

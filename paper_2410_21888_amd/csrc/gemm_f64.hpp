@@ -64,16 +64,19 @@ struct GemmParams {
   const uint8_t* skip;
   int32_t skip_nvir, skip_k0, skip_j0, skip_nocc;
   // pair_upper (same row/column to pair mapping): a tile all of whose pairs
-  // have j < k is not computed (their blocks are the transposes of computed ones).
-  int32_t pair_upper, pad;
+  // have pair_lo <= j < k is not computed (their blocks are the transposes of
+  // blocks the same launch computes).
+  int32_t pair_upper, pair_lo;
 };
 
 // True when the tile need not be computed (uniform): every occupied pair it
-// touches is screened out, or (pair_upper) has j < k.
+// touches is screened out, or (pair_upper) has pair_lo <= j < k.
 template <int BM, int BN>
 __device__ __forceinline__ bool tile_screened(const GemmParams& p, int tm, int tn) {
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-  if (p.pair_upper && p.skip_j0 + (min(p.N, n0 + BN) - 1) / p.skip_nvir < p.skip_k0 + m0 / p.skip_nvir) return true;
+  if (p.pair_upper && p.skip_j0 + (min(p.N, n0 + BN) - 1) / p.skip_nvir < p.skip_k0 + m0 / p.skip_nvir &&
+      p.skip_j0 + n0 / p.skip_nvir >= p.pair_lo)
+    return true;
   if (p.skip == nullptr) return false;
   const int64_t k_lo = m0 / p.skip_nvir, k_hi = (min(p.M, m0 + BM) - 1) / p.skip_nvir;
   const int64_t j_lo = n0 / p.skip_nvir, j_hi = (min(p.N, n0 + BN) - 1) / p.skip_nvir;

@@ -122,10 +122,10 @@ __device__ __forceinline__ void put_pair_energy(double sh, double sl, double* e_
 
 constexpr int AT = 32;
 
-// Whole-slab pair (k, j > k) of a slab holding every occupied row and column
-// (k0 = j0 = 0, ncols = nocc) whose block (j, k) was not computed: V_jk is
-// V_kj transposed, and D_jk = D_kj, so this workgroup forms both pairs from
-// V_kj alone.  For positions (a, b) and (b, a) of the block:
+// Pair (k, j > k) of a slab group k0.. that holds every column (j0 = 0,
+// ncols = nocc) and both rows k and j, whose block (j, k) was not computed:
+// V_jk is V_kj transposed, and D_jk = D_kj, so this workgroup forms both
+// pairs from V_kj alone.  For positions (a, b) and (b, a) of the block:
 //   X_kj[a,b] = V_kj[a,b] / D[a,b]    X_kj[b,a] = V_kj[b,a] / D[b,a]
 //   X_jk[a,b] = V_kj[b,a] / D[a,b]    X_jk[b,a] = V_kj[a,b] / D[b,a]
 // with D[a,b] = ((eps_k + eps_j) - eps_a) - eps_b, T = 2X - X^T for each
@@ -134,14 +134,14 @@ constexpr int AT = 32;
 // workgroup covers tile pairs [q0, q1) of the block.  VP and VQ are two
 // AT x (AT+1) LDS tiles of the caller.
 __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab, const double* eo, const double* ev,
-                                                       int nocc, int nvir, bool skip, double* e_pair, int k, int j,
-                                                       int q0, int q1, double* epart, double (*VP)[AT + 1],
+                                                       int nocc, int nvir, bool skip, double* e_pair, int k0, int k,
+                                                       int j, int q0, int q1, double* epart, double (*VP)[AT + 1],
                                                        double (*VQ)[AT + 1]) {
   const int64_t ld = (int64_t)nocc * nvir;
-  double* bkj = S + ((int64_t)k * nvir * nocc + j) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
-  double* bjk = S + ((int64_t)j * nvir * nocc + k) * nvir;
-  double* tkj = Tslab + ((int64_t)k * nvir * nocc + j) * nvir;
-  double* tjk = Tslab + ((int64_t)j * nvir * nocc + k) * nvir;
+  double* bkj = S + ((int64_t)(k - k0) * nvir * nocc + j) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
+  double* bjk = S + ((int64_t)(j - k0) * nvir * nocc + k) * nvir;
+  double* tkj = Tslab + ((int64_t)(k - k0) * nvir * nocc + j) * nvir;
+  double* tjk = Tslab + ((int64_t)(j - k0) * nvir * nocc + k) * nvir;
   const double ekj = eo[k] + eo[j];
   const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;
   const int nt = (nvir + AT - 1) / AT;
@@ -215,17 +215,25 @@ __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab,
 // is processed.
 // sym = 1 (energy only, slab holding j >= k0 only): pairs with j < k are left
 // to their mirror and e_kj is written to both e_kj and e_jk (e_ij = e_ji).
-// sym = 2 (whole slab, blocks j < k not computed): pairs j < k are left to
-// their mirror, pairs j > k form both blocks (amplitude_mirror_block; with
-// energy_only as sym = 1).  A screened pair (pair_skip, may be null) writes
+// sym = 2 (slab group k0..k0+g-1 over every column, j0 = 0): a pair whose
+// second orbital is also in the group is paired with its mirror; the
+// (ia|jb) GEMM has not computed the blocks j < k of those pairs, which are
+// left to their mirror, and pairs j > k form both blocks
+// (amplitude_mirror_block; with energy_only as sym = 1).  Other pairs are
+// formed on their own.  A screened pair (pair_skip, may be null) writes
 // e = 0 (and, unless energy_only, zero X and T) without reading V.
+__device__ __forceinline__ bool pair_mirrored(int sym, int k0, int g, int j) {
+  return sym == 1 || (sym == 2 && j >= k0 && j < k0 + g);
+}
+
 __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
-                                                int nvir, int k0, int j0, int ncols, int sym, int energy_only,
+                                                int nvir, int k0, int j0, int ncols, int sym, int g, int energy_only,
                                                 const uint8_t* pair_skip, double* e_pair, int kk, int jj, int w,
                                                 int W, double* epart_all) {
   __shared__ double XP[AT][AT + 1], XQ[AT][AT + 1];   // also the mirror path's V tiles
   const int k = k0 + kk, j = j0 + jj;
-  if (sym && j < k) return;
+  const bool paired = pair_mirrored(sym, k0, g, j);
+  if (paired && j < k) return;
   double* epart = (W > 1) ? epart_all + 2 * (((int64_t)kk * ncols + jj) * W + w) : nullptr;
   const int64_t ld = (int64_t)ncols * nvir;
   double* blk = S + ((int64_t)kk * nvir * ncols + jj) * nvir;  // element (a,b) at blk[a*ld + b]
@@ -233,12 +241,12 @@ __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const 
   const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
   const int nt = (nvir + AT - 1) / AT, npt = nt * (nt + 1) / 2;
   const int q0 = (int)((int64_t)npt * w / W), q1 = (int)((int64_t)npt * (w + 1) / W);
-  if (sym == 2 && !energy_only && j > k) {
-    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k, j, q0, q1, epart, XP, XQ);
+  if (sym == 2 && paired && !energy_only && j > k) {
+    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k0, k, j, q0, q1, epart, XP, XQ);
     return;
   }
   if (skip && energy_only) {
-    put_pair_energy(0.0, 0.0, e_pair, nocc, k, j, sym != 0, epart);
+    put_pair_energy(0.0, 0.0, e_pair, nocc, k, j, paired, epart);
     return;
   }
   const double ekj = eo[k] + eo[j];
@@ -305,23 +313,24 @@ __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const 
     }
     lds_barrier();
   }
-  put_pair_energy(sh, sl, e_pair, nocc, k, j, sym != 0, epart);
+  put_pair_energy(sh, sl, e_pair, nocc, k, j, paired, epart);
 }
 
 // One workgroup per (pair, w): blockIdx.x = (kk * ncols + jj) * W + w.
 __global__ __launch_bounds__(256) void amplitude_kernel(double* S, double* Tslab, const double* eo, const double* ev,
-                                                        int nocc, int nvir, int k0, int j0, int ncols, int sym,
+                                                        int nocc, int nvir, int k0, int j0, int ncols, int sym, int g,
                                                         int energy_only, const uint8_t* pair_skip, double* e_pair,
                                                         int W, double* epart, const int32_t* status) {
   if (*status != 0) return;
   const int p = blockIdx.x / W, w = blockIdx.x - p * W;
   const int kk = p / ncols, jj = p - kk * ncols;
-  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, j0, ncols, sym, energy_only, pair_skip, e_pair, kk, jj, w, W,
+  amplitude_block(S, Tslab, eo, ev, nocc, nvir, k0, j0, ncols, sym, g, energy_only, pair_skip, e_pair, kk, jj, w, W,
                   epart);
 }
 
 // e_kj from the W partial sums of each pair of a slab group (double-double,
-// added in order w = 0, 1, ...); with sym also e_jk.  One thread per pair.
+// added in order w = 0, 1, ...); for a pair paired with its mirror (see
+// amplitude_block) also e_jk.  One thread per pair.
 __global__ __launch_bounds__(256) void pair_energy_reduce_kernel(const double* epart, int W, int nocc, int k0, int j0,
                                                                  int g, int ncols, int sym, double* e_pair,
                                                                  const int32_t* status) {
@@ -330,11 +339,12 @@ __global__ __launch_bounds__(256) void pair_energy_reduce_kernel(const double* e
   if (p >= (int64_t)g * ncols) return;
   const int kk = (int)(p / ncols), jj = (int)(p - (int64_t)kk * ncols);
   const int k = k0 + kk, j = j0 + jj;
-  if (sym && j < k) return;
+  const bool paired = pair_mirrored(sym, k0, g, j);
+  if (paired && j < k) return;
   double h = 0.0, l = 0.0;
   for (int w = 0; w < W; ++w) dd_add(h, l, epart[2 * (p * W + w)], epart[2 * (p * W + w) + 1]);
   e_pair[(int64_t)k * nocc + j] = h + l;
-  if (sym) e_pair[(int64_t)j * nocc + k] = h + l;
+  if (paired) e_pair[(int64_t)j * nocc + k] = h + l;
 }
 
 // out[m*ldo + n] = (accumulate ? out : 0) + alpha * sum_{z < splits} W[z*zs + m*ldw + n],

@@ -260,12 +260,13 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   if (int rc = check_grid(nwg, "GEMM")) return rc;
   const bool vec = gemm_vec(gp, NC);
   double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
-  if (gp.pair_upper) {  // tiles not skipped: those with a pair j >= k (see tile_screened)
+  if (gp.pair_upper) {  // tiles not skipped: those with a pair j >= k or j < pair_lo (see tile_screened)
     int64_t kept = 0;
     for (int64_t tm = 0; tm < gp.tiles_m; ++tm) {
       const int64_t k_lo = gp.skip_k0 + tm * BM / gp.skip_nvir;
-      const int64_t first = std::max<int64_t>(0, cdiv((k_lo - gp.skip_j0) * gp.skip_nvir - BN + 1, BN));
-      kept += std::max<int64_t>(0, gp.tiles_n - first);
+      const int64_t below = std::max<int64_t>(0, cdiv((k_lo - gp.skip_j0) * gp.skip_nvir - BN + 1, BN));
+      const int64_t from = std::max<int64_t>(0, cdiv((gp.pair_lo - gp.skip_j0) * gp.skip_nvir, BN));
+      kept += gp.tiles_n - std::max<int64_t>(0, std::min<int64_t>(below, gp.tiles_n) - from);
     }
     ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
   }
@@ -532,9 +533,9 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
        })))
     return rc;
   const bool energy_only = !(P.gamma || P.density);
-  // whole slab (one group of every occupied orbital): blocks (k, j < k) are
-  // not computed and the amplitude pass forms them from their transposes
-  const bool mirror = !P.split && !energy_only && P.g >= nocc;
+  // pairs with both orbitals in the slab group: blocks (k, j < k) are not
+  // computed and the amplitude pass forms them from their transposes
+  const bool mirror = !P.split && !energy_only;
   int8_t* dbv = (int8_t*)(ws + P.off_dbv);
   int32_t* exv = (int32_t*)(ws + P.off_ev);
   int8_t* dbg = (int8_t*)(ws + P.off_dbg);
@@ -580,6 +581,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       gp.skip = skip; gp.skip_nvir = (int32_t)nvir; gp.skip_k0 = (int32_t)k0; gp.skip_j0 = (int32_t)j0;
       gp.skip_nocc = (int32_t)nocc;
       gp.pair_upper = (energy_only || mirror) ? 1 : 0;
+      gp.pair_lo = (int32_t)k0;
       // algorithmic FLOPs: unordered pairs whose first orbital is in the group
       // (energy only: exactly the pairs (k, j >= k) computed; otherwise the
       // unordered-pair share of the ordered pairs computed)
@@ -601,8 +603,8 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       if ((rc = check_grid(gc * ncols * W, "amplitude"))) return rc;
       if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
              hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols * W)), dim3(256), 0, st, V, T, eo, ev,
-                                (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, sym, energy_only ? 1 : 0, skip,
-                                ep, (int)W, epart, status);
+                                (int)nocc, (int)nvir, (int)k0, (int)j0, (int)ncols, sym, (int)gc,
+                                energy_only ? 1 : 0, skip, ep, (int)W, epart, status);
              if (W > 1)
                hipLaunchKernelGGL(pair_energy_reduce_kernel, dim3((unsigned)cdiv(gc * ncols, 256)), dim3(256), 0, st,
                                   (const double*)epart, (int)W, (int)nocc, (int)k0, (int)j0, (int)gc, (int)ncols, sym,

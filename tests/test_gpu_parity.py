@@ -55,6 +55,16 @@ def test_slab_groups(g):
     run_and_compare(synth.random_fragment(7, 40, 90, seed=77), opts=rm.rimp2.make_opts(slab_group=g))
 
 
+# Pairs with both orbitals in one slab group are formed from the block with
+# j > k alone.  These groups put GEMM tiles across pair and group boundaries
+# (nvir = 150 against 128-wide tiles, ragged last group) and split the
+# amplitude pass of a pair over several workgroups (nvir = 600, few pairs).
+@pytest.mark.parametrize("shape", [(10, 150, 130, 4), (4, 600, 64, 2), (5, 96, 70, 5)])
+def test_slab_group_mirror(shape):
+    nocc, nvir, naux, g = shape
+    run_and_compare(synth.random_fragment(nocc, nvir, naux, seed=nocc * nvir + g), opts=rm.rimp2.make_opts(slab_group=g))
+
+
 def test_output_subsets():
     f = synth.random_fragment(6, 37, 61, seed=8)
     B, eo, ev = f.arrays()
