@@ -246,6 +246,15 @@ bool gemm_vec(const GemmParams& gp, bool nc) {
   return kop_vec(gp.A, gp.K) && (nc ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
 }
 
+// The kernels' FAST path: 16-byte loads, every split a whole number of BK
+// chunks, every chunk inside one run of each K operand, and an even N for an
+// N-contiguous B (its column pairs past the edge are read at N - 2).
+bool gemm_fast(const GemmParams& gp, bool nc) {
+  auto runs = [&](const KOperand& o) { return o.kdiv >= gp.K || o.kdiv % kBK == 0; };
+  return gemm_vec(gp, nc) && gp.K % kBK == 0 && gp.kchunk % kBK == 0 && runs(gp.A) &&
+         (nc ? gp.N % 2 == 0 : runs(gp.Bk));
+}
+
 template <int BM, int BN, bool NC, int ROLE, bool TRI>
 int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
   gp.tiles_m = (int32_t)cdiv(gp.M, BM);
@@ -270,8 +279,12 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
     }
     ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
   }
+  const bool fast = gemm_fast(gp, NC);
   return traced(role, af, ef, ab, st, [&] {
-    if (vec)
+    if (fast)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, true>), dim3((unsigned)nwg), dim3(256), 0,
+                         st, gp);
+    else if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
     else
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, false, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);

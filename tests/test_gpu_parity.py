@@ -55,6 +55,17 @@ def test_slab_groups(g):
     run_and_compare(synth.random_fragment(7, 40, 90, seed=77), opts=rm.rimp2.make_opts(slab_group=g))
 
 
+# GEMMs whose reduction length is a multiple of 16 (and whose operand runs
+# hold whole 16-wide chunks) take the kernels' fast loader: 1, 2 and 3 chunks
+# per (ia|jb) reduction (naux = 16, 32, 48), edge tiles in every direction,
+# runs that wrap every few chunks (P_ij with nvir = 16, 48, 64, 144).
+@pytest.mark.parametrize("shape", [(3, 40, 16), (4, 24, 32), (2, 50, 48), (6, 16, 160), (3, 144, 96),
+                                   (5, 48, 64), (7, 64, 130)])
+def test_fast_loader_shapes(shape):
+    nocc, nvir, naux = shape
+    run_and_compare(synth.random_fragment(nocc, nvir, naux, seed=3 * nocc + nvir + naux))
+
+
 # Pairs with both orbitals in one slab group are formed from the block with
 # j > k alone.  These groups put GEMM tiles across pair and group boundaries
 # (nvir = 150 against 128-wide tiles, ragged last group) and split the
