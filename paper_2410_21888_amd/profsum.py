@@ -12,6 +12,12 @@ tooling; no part of the compute path).
         by what it read for the largest runtime copy kernel of the run (the
         1 GiB device-to-device copy `bench.py --calib-copy` makes), and tagged
         with the hash of the kernel sources it was measured on
+
+    python -m paper_2410_21888_amd.profsum mfma <counter_collection.csv>
+        per-role matrix-unit occupancy and clock from one `rocprofv3 --pmc
+        SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` run: busy cycles over all
+        SIMDs divided by (GPU-active cycles per XCC x SIMD count), and
+        GPU-active cycles per XCC over the dispatch's duration
 """
 from __future__ import annotations
 
@@ -137,6 +143,44 @@ def traffic(fetch_csv: str, write_csv: str):
     return out, {"fetch_scale": fs, "write_scale": ws, "fetch_copy_kib": f_copy, "write_copy_kib": w_copy}
 
 
+def _agent(counter_csv: str):
+    """(SIMD count, XCC count) of the GPU agent, from the agent_info.csv that
+    rocprofv3 writes beside the counter file."""
+    path = counter_csv.replace("counter_collection.csv", "agent_info.csv")
+    for r in csv.DictReader(open(path)):
+        if _num(r.get("Simd_Count", "")) > 0:
+            return int(_num(r["Simd_Count"])), max(1, int(_num(r.get("Num_Xcc", "1"))))
+    raise SystemExit("no GPU agent in %s" % path)
+
+
+def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
+    """{role: {launches, avg_ms, clock_ghz, mfma_busy}} from one PMC run of
+    SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (values summed over
+    dimensions; GRBM_GUI_ACTIVE counts once per XCC)."""
+    if not simds:
+        simds, xccs = _agent(counter_csv)
+    busy = _per_kernel(counter_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
+    gui = _per_kernel(counter_csv, "GRBM_GUI_ACTIVE")
+    dur = {}
+    for r in csv.DictReader(open(counter_csv)):
+        dur[r["Dispatch_Id"]] = _num(r["End_Timestamp"]) - _num(r["Start_Timestamp"])
+    acc = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    for key, (name, b) in busy.items():
+        role = role_of(name)
+        if role.startswith("(") or key not in gui:
+            continue
+        e = acc[role]
+        e[0] += 1
+        e[1] += dur.get(key, 0.0)
+        e[2] += b
+        e[3] += gui[key][1] / xccs
+    out = {}
+    for role, (n, ns, b, cyc) in acc.items():
+        out[role] = {"launches": n, "avg_ms": ns / n / 1e6, "clock_ghz": cyc / ns if ns > 0 else 0.0,
+                     "mfma_busy": b / (cyc * simds) if cyc > 0 else 0.0}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2410_21888_amd.profsum")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -147,7 +191,17 @@ def main(argv=None):
     h.add_argument("write_csv")
     h.add_argument("--workload", required=True)
     h.add_argument("--json", help="merge the result into this JSON file")
+    m = sub.add_parser("mfma")
+    m.add_argument("counter_csv")
     a = ap.parse_args(argv)
+    if a.cmd == "mfma":
+        print("Kernel sources hash: %s\n" % kernel_source_hash())
+        print("| role | launches | average ms | clock GHz | matrix units busy |")
+        print("|---|---|---|---|---|")
+        for role, e in sorted(mfma(a.counter_csv).items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"]):
+            print("| %s | %d | %.3f | %.2f | %.1f%% |" % (role, e["launches"], e["avg_ms"], e["clock_ghz"],
+                                                         100.0 * e["mfma_busy"]))
+        return 0
     if a.cmd == "trace":
         print("Kernel sources hash: %s\n" % kernel_source_hash())
         print(trace_summary(a.stats_csv))

@@ -23,6 +23,8 @@ def test_roles_of_kernel_symbols():
     assert profsum.role_of(INTS) == "ints_gemm"
     assert profsum.role_of(GAMMA) == "gamma_gemm"
     assert profsum.role_of(GAMMA.replace("true, 1", "false, 1")) == "gamma_metric"
+    # the instantiation with the two-chunks-ahead loader carries one more argument
+    assert profsum.role_of(INTS.replace("true, false>", "true, false, true>")) == "ints_gemm"
     assert profsum.role_of("void rimp2::gemm_f64_grouped<64, 64, 16, false, 3, true, true>(rimp2::GemmGroup)") == "pij_gemm"
     assert profsum.role_of("rimp2::amplitude_kernel(double*, ...)") == "amplitude"
     assert profsum.role_of("__amd_rocclr_copyBuffer") == "(runtime copy)"
@@ -44,3 +46,25 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     assert profsum.main(["traffic", str(f), str(w), "--workload", "w", "--json", str(out)]) == 0
     d = json.load(open(out))
     assert d["w"]["ints_gemm"]["source_hash"] == profsum.kernel_source_hash()
+
+
+def test_mfma_occupancy_and_clock(tmp_path):
+    c = tmp_path / "m_counter_collection.csv"
+    a = tmp_path / "m_agent_info.csv"
+    with open(a, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Node_Id", "Simd_Count", "Num_Xcc"])
+        w.writerow([0, 0, 0])          # the CPU agent
+        w.writerow([1, 1024, 8])
+    with open(c, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HEAD)
+        # 1 ms at 2.4 GHz on 8 XCCs, matrix units busy 90% of 1024 SIMDs' cycles
+        for i, (cn, v) in enumerate((("GRBM_GUI_ACTIVE", 8 * 2.4e6), ("SQ_VALU_MFMA_BUSY_CYCLES", 0.9 * 2.4e6 * 1024))):
+            w.writerow([7, 7, "Agent 1", 1, 1, 1, 256, 1, INTS, 256, 0, 0, 64, 0, 32, cn, v, 1000000, 2000000])
+    r = profsum.mfma(str(c))
+    e = r["ints_gemm"]
+    assert e["launches"] == 1
+    assert abs(e["avg_ms"] - 1.0) < 1e-12
+    assert abs(e["clock_ghz"] - 2.4) < 1e-9
+    assert abs(e["mfma_busy"] - 0.9) < 1e-12
