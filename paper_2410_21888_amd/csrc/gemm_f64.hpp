@@ -134,7 +134,7 @@ struct GemmLds {
 
 // One output tile (tm, tn) of split z.  Ends with a workgroup barrier, so the
 // LDS can be reused by the next tile.
-template <int BM, int BN, int BK, bool B_NCONTIG, bool VEC, bool TRI, bool FAST>
+template <int BM, int BN, int BK, bool B_NCONTIG, bool VEC, bool TRI, int FAST>
 __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, int z, GemmLds<BM, BN, BK>& lds) {
   static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 8 == 0, "tile shape");
   typedef double d2 __attribute__((ext_vector_type(2)));
@@ -264,22 +264,29 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  // FAST (chosen by the host when every chunk is full and lies within one run
-  // of each K operand, with 16-byte loads): a branch-free loader issues each
-  // chunk's global loads two chunks ahead into two register sets.  Rows (and
-  // N-contiguous column pairs) past the edge of the matrix read the last valid
-  // ones instead; they only reach accumulators that are never stored.  The
-  // loads are unconditional (after the end the last chunk is loaded again), so
-  // the compiler's wait counts stay exact, and the barriers order LDS only, so
-  // the loads stay in flight across them.  Both paths sum every output
-  // element in the same order.
-  if constexpr (FAST) {
-    if (nchunks > 0) {
+  // FAST > 0 (chosen by the host: 16-byte loads, an even reduction length,
+  // runs of the K operands at least one chunk long): the split's full chunks
+  // go through a branch-free loader that issues each chunk's global loads two
+  // chunks ahead into two register sets.  Rows (and N-contiguous column
+  // pairs) past the edge of the matrix read the last valid ones, which only
+  // reach accumulators that are never stored.  The loads are unconditional
+  // (after the last full chunk it is loaded again), so the compiler's wait
+  // counts stay exact, and the barriers order LDS only, so the loads stay in
+  // flight across them.  Chunk starts advance by uniform run steps; with
+  // FAST = 2 (runs shorter than the reduction and not a multiple of the chunk)
+  // a thread whose pair lies in the next run adds one run step.  A ragged
+  // last chunk is then loaded with per-element masks and run on its own.
+  // Every path sums each output element in the same order.
+  if constexpr (FAST > 0) {
+    const int nfull = (int)((kend - kbeg) / BK);
+    if (nfull > 0) {
       d2 xa[2][AN], xb[2][BREG];
-      // next chunk to load: (run, offset in run) of each K operand, k row of an N-contiguous B
-      int64_t qa = kbeg / p.A.kdiv, pa = kbeg - qa * p.A.kdiv;
-      int64_t qb = 0, pb = 0, kn = kbeg;
-      if (!B_NCONTIG) { qb = kbeg / p.Bk.kdiv; pb = kbeg - qb * p.Bk.kdiv; }
+      // start of the next chunk to load (uniform): offset of each K operand
+      // and its position in the current run
+      int64_t oa = 0, pa = 0, ob = 0, pb = 0;
+      { const int64_t q = kbeg / p.A.kdiv; pa = kbeg - q * p.A.kdiv; oa = q * p.A.ks1 + pa; }
+      if (!B_NCONTIG) { const int64_t q = kbeg / p.Bk.kdiv; pb = kbeg - q * p.Bk.kdiv; ob = q * p.Bk.ks1 + pb; }
+      else { ob = kbeg * p.Bn.ld; }
       int nload = 0;
       const double* ap[AN];
 #pragma unroll
@@ -293,21 +300,25 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
 #pragma unroll
         for (int s = 0; s < BREG; ++s) bp[s] = p.Bn.base + (int64_t)(kn0 + s * NSTEP) * p.Bn.ld + n;
       }
+      // this thread's extra offset when its pair lies in the run after the chunk start's
+      auto wrap = [&](const KOperand& o, int64_t pos) -> int64_t {
+        return (FAST == 2 && pos + kk >= o.kdiv) ? o.ks1 - o.kdiv : 0;
+      };
       auto fload = [&](d2 (&da)[AN], d2 (&db)[BREG]) {
-        const int64_t oa = qa * p.A.ks1 + pa;
+        const int64_t xa_ = oa + wrap(p.A, pa);
 #pragma unroll
-        for (int s = 0; s < AN; ++s) da[s] = *(const d2*)(ap[s] + oa);
-        const int64_t ob = B_NCONTIG ? kn * p.Bn.ld : qb * p.Bk.ks1 + pb;
+        for (int s = 0; s < AN; ++s) da[s] = *(const d2*)(ap[s] + xa_);
+        const int64_t xb_ = B_NCONTIG ? ob : ob + wrap(p.Bk, pb);
 #pragma unroll
-        for (int s = 0; s < BREG; ++s) db[s] = *(const d2*)(bp[s] + ob);
-        if (++nload < nchunks) {
-          pa += BK;
-          if (pa == p.A.kdiv) { pa = 0; ++qa; }
+        for (int s = 0; s < BREG; ++s) db[s] = *(const d2*)(bp[s] + xb_);
+        if (++nload < nfull) {
+          oa += BK; pa += BK;
+          if (pa >= p.A.kdiv) { pa -= p.A.kdiv; oa += p.A.ks1 - p.A.kdiv; }
           if (B_NCONTIG) {
-            kn += BK;
+            ob += (int64_t)BK * p.Bn.ld;
           } else {
-            pb += BK;
-            if (pb == p.Bk.kdiv) { pb = 0; ++qb; }
+            ob += BK; pb += BK;
+            if (pb >= p.Bk.kdiv) { pb -= p.Bk.kdiv; ob += p.Bk.ks1 - p.Bk.kdiv; }
           }
         }
       };
@@ -318,7 +329,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
       // chunk c (c % 2 == S) from LDS buffer S; chunk c+1 waits in register set S^1
       auto step = [&](int c, auto set) {
         constexpr int S = decltype(set)::value;
-        const bool more = c + 1 < nchunks;
+        const bool more = c + 1 < nfull;
         fload(xa[S], xb[S]);
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
@@ -334,11 +345,54 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
         lds_sync();
       };
       int c = 0;
-      for (; c + 1 < nchunks; c += 2) {
+      for (; c + 1 < nfull; c += 2) {
         step(c, std::integral_constant<int, 0>{});
         step(c + 1, std::integral_constant<int, 1>{});
       }
-      if (c < nchunks) step(c, std::integral_constant<int, 0>{});
+      if (c < nfull) step(c, std::integral_constant<int, 0>{});
+    }
+    if (nfull < nchunks) {
+      // the ragged last chunk: per-element masks (pairs, as the reduction length is even)
+      const int64_t kt = kbeg + (int64_t)nfull * BK;
+      const d2 zero = {0.0, 0.0};
+      {
+        const int64_t k = kt + kk;
+        const bool in = k < kend;
+        const int64_t q = in ? k / p.A.kdiv : 0;
+        const int64_t off = in ? q * p.A.ks1 + (k - q * p.A.kdiv) : 0;
+#pragma unroll
+        for (int s = 0; s < AN; ++s)
+          ra[s] = in ? *(const d2*)(p.A.base + min(m0 + r0 + s * RSTEP, p.M - 1) * p.A.rs + off) : zero;
+      }
+      if (!B_NCONTIG) {
+        const int64_t k = kt + kk;
+        const bool in = k < kend;
+        const int64_t q = in ? k / p.Bk.kdiv : 0;
+        const int64_t off = in ? q * p.Bk.ks1 + (k - q * p.Bk.kdiv) : 0;
+#pragma unroll
+        for (int s = 0; s < BREG; ++s)
+          rb[s] = in ? *(const d2*)(p.Bk.base + min(n0 + r0 + s * RSTEP, p.N - 1) * p.Bk.rs + off) : zero;
+      } else {
+        const int64_t n = min(n0 + nn, p.N - 2);
+#pragma unroll
+        for (int s = 0; s < BREG; ++s) {
+          const int64_t k = kt + kn0 + s * NSTEP;
+          rb[s] = k < kend ? *(const d2*)(p.Bn.base + k * p.Bn.ld + n) : zero;
+        }
+      }
+      store_chunk(0);
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        double a[MI], b[NI];
+        read_frag(0, ks, a, b);
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
     }
   } else if (nchunks > 0) {
     load_chunk(0);
@@ -385,7 +439,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
 
 
 // One workgroup per (split, tile); the hardware id is remapped XCD-aware.
-template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI, bool FAST = false>
+template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI, int FAST = 0>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
   if (p.status != nullptr && *p.status != 0) return;
   __shared__ GemmLds<BM, BN, BK> lds;
@@ -410,7 +464,7 @@ struct GemmGroup {
   unsigned long long* counter;
 };
 
-template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI>
+template <int BM, int BN, int BK, bool B_NCONTIG, int ROLE, bool VEC, bool TRI, int FAST = 0>
 __global__ __launch_bounds__(256, 2) void gemm_f64_grouped(GemmGroup G) {
   __shared__ GemmLds<BM, BN, BK> lds;
   __shared__ long long item;
@@ -434,7 +488,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_grouped(GemmGroup G) {
     int tm, tn;
     decode_tile<TRI>(p, u - z * ntiles, tm, tn);
     if (tile_screened<BM, BN>(p, tm, tn)) continue;
-    gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, false>(p, tm, tn, z, lds);
+    gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, FAST>(p, tm, tn, z, lds);
   }
 }
 

@@ -33,11 +33,8 @@ extern "C" int rimp2_gamma_metric(int32_t nocc, int32_t nvir, int32_t naux, cons
   if (nwg > 0xffffffffLL / 256) return fail(RIMP2_EINVAL, "grid too large");
   const bool vec = (uintptr_t)Gamma % 16 == 0 && (uintptr_t)Jm % 16 == 0 && n % 2 == 0;
   hipStream_t st = (hipStream_t)stream;
-  if (vec && n % 16 == 0)   // whole 16-wide chunks: the loader running two chunks ahead
-    hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, false, ROLE_GAMMA, true, false, true>), dim3((unsigned)nwg),
-                       dim3(256), 0, st, gp);
-  else if (vec)
-    hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, false, ROLE_GAMMA, true, false>), dim3((unsigned)nwg),
+  if (vec)   // the loader running two chunks ahead (n is even, both operands plain)
+    hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, false, ROLE_GAMMA, true, false, 1>), dim3((unsigned)nwg),
                        dim3(256), 0, st, gp);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 16, false, ROLE_GAMMA, false, false>), dim3((unsigned)nwg),

@@ -246,14 +246,18 @@ bool gemm_vec(const GemmParams& gp, bool nc) {
   return kop_vec(gp.A, gp.K) && (nc ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
 }
 
-// The kernels' FAST path: 16-byte loads, every split a whole number of BK
-// chunks, every chunk inside one run of each K operand, and an even N for an
-// N-contiguous B (its column pairs past the edge are read at N - 2).
-bool gemm_fast(const GemmParams& gp, bool nc) {
-  auto runs = [&](const KOperand& o) { return o.kdiv >= gp.K || o.kdiv % kBK == 0; };
-  return gemm_vec(gp, nc) && gp.K % kBK == 0 && gp.kchunk % kBK == 0 && runs(gp.A) &&
-         (nc ? gp.N % 2 == 0 : runs(gp.Bk));
+// The kernels' FAST path (returns 0 when it does not apply): 16-byte loads,
+// an even reduction length (no reduction pair straddles the end), runs of the
+// K operands at least one chunk long (a chunk crosses at most one run
+// boundary) and an even N for an N-contiguous B (its column pairs past the
+// edge are read at N - 2).  2 when a K operand's runs can end inside a chunk.
+int fast_level(const GemmParams& gp, bool nc) {
+  auto runs = [&](const KOperand& o) { return o.kdiv >= gp.K || o.kdiv >= kBK; };
+  auto wraps = [&](const KOperand& o) { return o.kdiv < gp.K && o.kdiv % kBK != 0; };
+  if (!(gp.K % 2 == 0 && gp.kchunk % kBK == 0 && runs(gp.A) && (nc ? gp.N % 2 == 0 : runs(gp.Bk)))) return 0;
+  return (wraps(gp.A) || (!nc && wraps(gp.Bk))) ? 2 : 1;
 }
+int gemm_fast(const GemmParams& gp, bool nc) { return gemm_vec(gp, nc) ? fast_level(gp, nc) : 0; }
 
 template <int BM, int BN, bool NC, int ROLE, bool TRI>
 int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
@@ -279,10 +283,13 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
     }
     ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
   }
-  const bool fast = gemm_fast(gp, NC);
+  const int fast = gemm_fast(gp, NC);
   return traced(role, af, ef, ab, st, [&] {
-    if (fast)
-      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, true>), dim3((unsigned)nwg), dim3(256), 0,
+    if (fast == 1)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, 1>), dim3((unsigned)nwg), dim3(256), 0,
+                         st, gp);
+    else if (fast == 2)
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, 2>), dim3((unsigned)nwg), dim3(256), 0,
                          st, gp);
     else if (vec)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI>), dim3((unsigned)nwg), dim3(256), 0, st, gp);
@@ -712,6 +719,10 @@ int want_of(const double* Gam, const double* Pij, const double* Pab, int* want) 
 
 
 // ---- batches -----------------------------------------------------------------
+// Grouped GEMM lists of a wave: 4 roles x 2 candidate tiles x 4 loaders
+// (0: two chunks ahead, 1: the same with runs ending inside chunks, 2: the
+// general loader with 16-byte loads, 3: the general loader, 8-byte loads).
+constexpr int kGLists = 32;
 struct GemmList {            // grouped GEMM problems of one role in one wave
   std::vector<GemmParams> p;
   std::vector<int64_t> prefix;  // work items (tiles x splits)
@@ -723,11 +734,11 @@ struct Wave {
   size_t bytes = 0;             // tables + fragment partitions
   // offsets within the tables
   size_t o_fs, o_idx, o_amp, o_amp_pre, o_red, o_red_pre, o_cnt;
-  // GEMM lists, index glist(role, candidate tile, 16-byte loads): every GEMM
-  // is listed once per candidate tile shape (kBatchTile)
-  size_t o_g[16], o_pre[16];
-  int n_g[16];
-  int64_t items_g[16];
+  // GEMM lists, index glist(role, candidate tile, loader): every GEMM is
+  // listed once per candidate tile shape (kBatchTile)
+  size_t o_g[kGLists], o_pre[kGLists];
+  int n_g[kGLists];
+  int64_t items_g[kGLists];
   uint64_t sig = 0;             // hash of the wave's fragment sizes (autotuner key)
   int namp, nred_ab, nred_ij;
   int64_t amp_blocks, red_blocks_ab, red_blocks_ij;
@@ -760,7 +771,13 @@ bool kop_vec_rel(const KOperand& o, int64_t K) {
 // first) and list index.
 const int kBatchRole[4] = {R_INTS, R_GAMMA, R_PAB, R_PIJ};
 const int kBatchTile[4][2] = {{128, 64}, {128, 64}, {128, 64}, {64, 32}};
-int glist(int rho, int cand, bool vec) { return (rho * 2 + cand) * 2 + (vec ? 0 : 1); }
+int glist(int rho, int cand, int loader) { return (rho * 2 + cand) * 4 + loader; }
+// loader of a grouped GEMM (see kGLists); vec: 16-byte loads apply
+int loader_of(const GemmParams& g, bool nc, bool vec) {
+  if (!vec) return 3;
+  const int f = fast_level(g, nc);
+  return f ? f - 1 : 2;
+}
 
 // tiles, splits and group size of a GEMM, as launch_gemm sets them
 int64_t finalize_gemm(GemmParams& gp, int BM, int BN, bool tri) {
@@ -840,11 +857,11 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     W.o_amp_pre = place(t, sizeof(int64_t) * (n + 1));
     W.o_red = place(t, sizeof(ReduceDesc) * 2 * n);
     W.o_red_pre = place(t, sizeof(int64_t) * (2 * n + 1));
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kGLists; ++r) {
       W.o_g[r] = place(t, sizeof(GemmParams) * n);
       W.o_pre[r] = place(t, sizeof(int64_t) * (n + 1));
     }
-    W.o_cnt = place(t, 16 * sizeof(unsigned long long));
+    W.o_cnt = place(t, kGLists * sizeof(unsigned long long));
     W.tab_bytes = t;
     W.host_off = tab;
     tab = align_up(tab + t);
@@ -859,14 +876,14 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     std::vector<int64_t> amp_pre(n + 1, 0);
     std::vector<ReduceDesc> red;
     std::vector<int64_t> red_pre(1, 0);
-    GemmList gl[16];
+    GemmList gl[kGLists];
     for (auto& l : gl) l.prefix.assign(1, 0);
     // every GEMM goes to the lists of both candidate tiles of its role
     auto add = [&](int rho, const GemmParams& g0, bool vec) {
       for (int c = 0; c < 2; ++c) {
         GemmParams g = g0;
         const int64_t items = finalize_gemm(g, kBatchTile[rho][c], kBatchTile[rho][c], rho >= 2);
-        GemmList& l = gl[glist(rho, c, vec)];
+        GemmList& l = gl[glist(rho, c, loader_of(g, rho == 1, vec))];
         l.p.push_back(g);
         l.prefix.push_back(l.prefix.back() + items);
       }
@@ -935,7 +952,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     W.amp_blocks = amp_pre[n];
     W.nred_ab = (int)red.size();
     W.red_blocks_ab = red_pre.back();
-    for (int r = 0; r < 16; ++r) { W.n_g[r] = (int)gl[r].p.size(); W.items_g[r] = gl[r].prefix.back(); }
+    for (int r = 0; r < kGLists; ++r) { W.n_g[r] = (int)gl[r].p.size(); W.items_g[r] = gl[r].prefix.back(); }
     W.sig = sig;
     char* blob = B->blob.data() + W.host_off;
     auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) memcpy(blob + off, src, bytes); };
@@ -945,7 +962,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     put(W.o_amp_pre, amp_pre.data(), sizeof(int64_t) * (n + 1));
     put(W.o_red, red.data(), sizeof(ReduceDesc) * red.size());
     put(W.o_red_pre, red_pre.data(), sizeof(int64_t) * red_pre.size());
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kGLists; ++r) {
       put(W.o_g[r], gl[r].p.data(), sizeof(GemmParams) * gl[r].p.size());
       put(W.o_pre[r], gl[r].prefix.data(), sizeof(int64_t) * gl[r].prefix.size());
     }
@@ -955,31 +972,38 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
   return RIMP2_OK;
 }
 
-template <int BM, int BN, bool NC, int ROLE, bool VEC, bool TRI>
+template <int BM, int BN, bool NC, int ROLE, bool VEC, bool TRI, int FAST>
 int launch_grouped(const GemmGroup& G, int64_t items, int role, hipStream_t st) {
   if (G.nprob == 0 || items == 0) return RIMP2_OK;
   const int64_t grid = std::min<int64_t>(items, kSlots);
   return traced(role, 0, 0, 0, st, [&] {
-    hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, kBK, NC, ROLE, VEC, TRI>), dim3((unsigned)grid), dim3(256), 0, st, G);
+    hipLaunchKernelGGL((gemm_f64_grouped<BM, BN, kBK, NC, ROLE, VEC, TRI, FAST>), dim3((unsigned)grid), dim3(256), 0,
+                       st, G);
   });
 }
 
 // One grouped launch of batch role rho with candidate tile c (kBatchTile) over
-// its list with or without 16-byte loads.
-int launch_group_list(int rho, int c, bool vec, const GemmGroup& G, int64_t items, hipStream_t st) {
+// its list of one loader (see kGLists).
+int launch_group_list(int rho, int c, int loader, const GemmGroup& G, int64_t items, hipStream_t st) {
   const int role = kBatchRole[rho];
-#define RIMP2_G(BM, NC, ROLE, TRI)                                                        \
-  return vec ? launch_grouped<BM, BM, NC, ROLE, true, TRI>(G, items, role, st)            \
-             : launch_grouped<BM, BM, NC, ROLE, false, TRI>(G, items, role, st)
+// (the 128 x 128 Gamma tile with the fast loader runs out of registers in the
+// persistent loop: its fast lists take the general 16-byte loader)
+#define RIMP2_G(BM, NC, ROLE, TRI, F1, F2)                                                            \
+  switch (loader) {                                                                                   \
+    case 0: return launch_grouped<BM, BM, NC, ROLE, true, TRI, F1>(G, items, role, st);               \
+    case 1: return launch_grouped<BM, BM, NC, ROLE, true, TRI, F2>(G, items, role, st);               \
+    case 2: return launch_grouped<BM, BM, NC, ROLE, true, TRI, 0>(G, items, role, st);                \
+    default: return launch_grouped<BM, BM, NC, ROLE, false, TRI, 0>(G, items, role, st);              \
+  }
   switch (rho * 2 + c) {
-    case 0: RIMP2_G(128, false, ROLE_INTS, false);
-    case 1: RIMP2_G(64, false, ROLE_INTS, false);
-    case 2: RIMP2_G(128, true, ROLE_GAMMA, false);
-    case 3: RIMP2_G(64, true, ROLE_GAMMA, false);
-    case 4: RIMP2_G(128, false, ROLE_PAB, true);
-    case 5: RIMP2_G(64, false, ROLE_PAB, true);
-    case 6: RIMP2_G(64, false, ROLE_PIJ, true);
-    default: RIMP2_G(32, false, ROLE_PIJ, true);
+    case 0: RIMP2_G(128, false, ROLE_INTS, false, 1, 2);
+    case 1: RIMP2_G(64, false, ROLE_INTS, false, 1, 2);
+    case 2: RIMP2_G(128, true, ROLE_GAMMA, false, 0, 0);
+    case 3: RIMP2_G(64, true, ROLE_GAMMA, false, 1, 2);
+    case 4: RIMP2_G(128, false, ROLE_PAB, true, 1, 2);
+    case 5: RIMP2_G(64, false, ROLE_PAB, true, 1, 2);
+    case 6: RIMP2_G(64, false, ROLE_PIJ, true, 1, 2);
+    default: RIMP2_G(32, false, ROLE_PIJ, true, 1, 2);
   }
 #undef RIMP2_G
 }
@@ -1014,7 +1038,7 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
     auto at = [&](size_t o) { return ws + W.host_off + o; };
     if ((rc = traced(R_STATUS, 0, 0, 0, st, [&] {
            // relocate every table (GEMM lists are contiguous per role; relocate each list)
-           for (int r = 0; r < 16; ++r)
+           for (int r = 0; r < kGLists; ++r)
              if (W.n_g[r])
                hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(W.n_g[r], 256)), dim3(256), 0, st, ws,
                                   (GemmParams*)at(W.o_g[r]), W.n_g[r], (AmpDesc*)nullptr, 0, (ReduceDesc*)nullptr, 0,
@@ -1023,7 +1047,8 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
            hipLaunchKernelGGL(relocate_tables_kernel, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, ws, gp0, 0,
                               (AmpDesc*)at(W.o_amp), n, (ReduceDesc*)at(W.o_red), W.nred_ab, (FragSmall*)at(W.o_fs),
                               n);
-           hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt), 16);
+           hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt),
+                              kGLists);
            hipLaunchKernelGGL(gap_check_grouped, dim3((unsigned)n), dim3(256), 0, st, (const FragSmall*)at(W.o_fs));
          })))
       return rc;
@@ -1034,12 +1059,17 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
     // each GEMM role: the lists of one candidate tile (with autotuning the
     // tuned one for this wave's fragment sizes)
     auto run_role = [&](int rho) -> int {
-      const int64_t i0 = W.items_g[glist(rho, 0, true)] + W.items_g[glist(rho, 0, false)];
+      auto items_of = [&](int c) {
+        int64_t n = 0;
+        for (int k = 0; k < 4; ++k) n += W.items_g[glist(rho, c, k)];
+        return n;
+      };
+      const int64_t i0 = items_of(0);
       if (i0 == 0) return RIMP2_OK;
       auto launch = [&](int c) -> int {
-        for (int vec = 1; vec >= 0; --vec) {
-          const int li = glist(rho, c, vec != 0);
-          const int r = launch_group_list(rho, c, vec != 0, grp(li), W.items_g[li], st);
+        for (int k = 0; k < 4; ++k) {
+          const int li = glist(rho, c, k);
+          const int r = launch_group_list(rho, c, k, grp(li), W.items_g[li], st);
           if (r) return r;
         }
         return RIMP2_OK;
@@ -1047,7 +1077,7 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
       if (!B->autotune) return launch(0);
       int dev = 0;
       HIP_TRY(hipGetDevice(&dev));
-      const int64_t i1 = W.items_g[glist(rho, 1, true)] + W.items_g[glist(rho, 1, false)];
+      const int64_t i1 = items_of(1);
       const TuneKey key{dev, kBatchRole[rho], 2, n, i0, i1, (int64_t)(W.sig >> 1)};
       const TileShape cand[2] = {{kBatchTile[rho][0], kBatchTile[rho][0]}, {kBatchTile[rho][1], kBatchTile[rho][1]}};
       return tuned(key, 2, cand, st, launch);

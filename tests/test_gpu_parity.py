@@ -55,12 +55,14 @@ def test_slab_groups(g):
     run_and_compare(synth.random_fragment(7, 40, 90, seed=77), opts=rm.rimp2.make_opts(slab_group=g))
 
 
-# GEMMs whose reduction length is a multiple of 16 (and whose operand runs
-# hold whole 16-wide chunks) take the kernels' fast loader: 1, 2 and 3 chunks
-# per (ia|jb) reduction (naux = 16, 32, 48), edge tiles in every direction,
-# runs that wrap every few chunks (P_ij with nvir = 16, 48, 64, 144).
+# GEMMs with an even reduction length and operand runs of at least 16 take
+# the kernels' fast loader: 1, 2 and 3 chunks per (ia|jb) reduction
+# (naux = 16, 32, 48), ragged last chunks (naux = 2, 18, 34, 54, 100; Gamma's
+# K = nocc nvir = 120, 150), edge tiles in every direction, and runs that
+# start mid-chunk (P_ij with nvir = 24, 30, 50; P_ab with L = 120, 150).
 @pytest.mark.parametrize("shape", [(3, 40, 16), (4, 24, 32), (2, 50, 48), (6, 16, 160), (3, 144, 96),
-                                   (5, 48, 64), (7, 64, 130)])
+                                   (5, 48, 64), (7, 64, 130), (4, 30, 54), (3, 40, 18), (6, 20, 2),
+                                   (2, 16, 34), (6, 25, 100), (5, 30, 36)])
 def test_fast_loader_shapes(shape):
     nocc, nvir, naux = shape
     run_and_compare(synth.random_fragment(nocc, nvir, naux, seed=3 * nocc + nvir + naux))
