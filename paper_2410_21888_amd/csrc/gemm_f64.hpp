@@ -16,10 +16,11 @@
 // register r of lane l holds D[4r + l/16][l%16].  Operand tiles are staged
 // k-major in LDS (double-buffered, one barrier per BK chunk).  Global loads
 // are 16 bytes (two consecutive reduction indices, or two consecutive columns
-// of an N-contiguous operand) when the operands allow it (VEC); interior
-// tiles take an unmasked path with loop-invariant row offsets.  The next
-// chunk's loads are issued before the current chunk's MFMAs and stored to LDS
-// halfway through them.
+// of an N-contiguous operand) when the operands allow it (VEC).  Two loaders:
+// the general one (FAST = 0) issues the next chunk's loads before the current
+// chunk's MFMAs and stores them to LDS halfway through them, with masks on
+// edge tiles; the fast one (FAST = 1, 2; chosen by the host) keeps loads two
+// chunks ahead without any branch around them (see gemm_tile).
 //
 // Triangular launches (TRI): for a symmetric result only tiles with
 // tile_m <= tile_n are computed; every element m < n is written at (m, n) and

@@ -43,13 +43,46 @@ _GEMM_ROLES = {"0": "ints_gemm", "1": "gamma_gemm", "2": "pab_gemm", "3": "pij_g
 FRAGMENT_SOURCES = ("batch.hpp", "common.hpp", "gemm_f64.hpp", "kernels.hpp", "rimp2.hip", "split_int8.hpp")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the fragment path's kernel sources (names and contents)."""
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments (string and character literals kept)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
+def sources_hash(read) -> str:
+    """Hash of the fragment path's kernel sources: names, and contents without
+    comments with every run of white space read as one blank; read(name)
+    returns a file's text."""
     h = hashlib.sha256()
     for fn in FRAGMENT_SOURCES:
-        with open(os.path.join(CSRC, fn), "rb") as f:
-            h.update(fn.encode() + f.read())
+        h.update(fn.encode() + " ".join(strip_comments(read(fn)).split()).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash() -> str:
+    """Hash of the fragment path's kernel sources as they are in the tree
+    (comments do not enter it)."""
+    def read(fn):
+        with open(os.path.join(CSRC, fn), encoding="utf-8") as f:
+            return f.read()
+    return sources_hash(read)
 
 
 def role_of(name: str) -> str:
@@ -74,6 +107,11 @@ def role_of(name: str) -> str:
     return "(other)"
 
 
+def _rows(path: str) -> list:
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
 def _num(x: str) -> float:
     return float(x) if x not in ("", None) else 0.0
 
@@ -88,7 +126,7 @@ def _col(r: dict, *names) -> float:
 def trace_summary(stats_csv: str) -> str:
     """Markdown table of a kernel statistics CSV (rocprofv3 --stats, or
     rocpd2summary's kernels summary)."""
-    rows = list(csv.DictReader(open(stats_csv)))
+    rows = _rows(stats_csv)
     tot_of = lambda r: _col(r, "TotalDurationNs", "Duration (Nsec)")
     total = sum(tot_of(r) for r in rows) or 1.0
     out = ["| role | kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|---|"]
@@ -107,7 +145,7 @@ def _per_kernel(counter_csv: str, counter: str):
     """{dispatch id: (kernel name, value)} for one counter (values summed over
     dimensions of the same dispatch)."""
     d = {}
-    for r in csv.DictReader(open(counter_csv)):
+    for r in _rows(counter_csv):
         if r["Counter_Name"] != counter:
             continue
         key = r["Dispatch_Id"]
@@ -147,7 +185,7 @@ def _agent(counter_csv: str):
     """(SIMD count, XCC count) of the GPU agent, from the agent_info.csv that
     rocprofv3 writes beside the counter file."""
     path = counter_csv.replace("counter_collection.csv", "agent_info.csv")
-    for r in csv.DictReader(open(path)):
+    for r in _rows(path):
         if _num(r.get("Simd_Count", "")) > 0:
             return int(_num(r["Simd_Count"])), max(1, int(_num(r.get("Num_Xcc", "1"))))
     raise SystemExit("no GPU agent in %s" % path)
@@ -162,7 +200,7 @@ def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
     busy = _per_kernel(counter_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
     gui = _per_kernel(counter_csv, "GRBM_GUI_ACTIVE")
     dur = {}
-    for r in csv.DictReader(open(counter_csv)):
+    for r in _rows(counter_csv):
         dur[r["Dispatch_Id"]] = _num(r["End_Timestamp"]) - _num(r["Start_Timestamp"])
     acc = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
     for key, (name, b) in busy.items():
@@ -217,7 +255,10 @@ def main(argv=None):
         print("| %s | %d | %.4g | %.4g | %.4g |" % (role, e["launches"], e["fetch_kib_raw"], e["write_kib_raw"],
                                                     e["bytes_per_launch"]))
     if a.json:
-        d = json.load(open(a.json)) if os.path.exists(a.json) else {}
+        d = {}
+        if os.path.exists(a.json):
+            with open(a.json) as fh:
+                d = json.load(fh)
         d[a.workload] = {r: dict(e, source_hash=src) for r, e in roles.items()}
         d["calibration"] = cal
         with open(a.json, "w") as f:

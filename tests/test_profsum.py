@@ -44,7 +44,8 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     assert abs(roles["gamma_gemm"]["bytes_per_launch"] - (10.0 * 2 + 1.0) * 1024) < 1e-6
     out = tmp_path / "t.json"
     assert profsum.main(["traffic", str(f), str(w), "--workload", "w", "--json", str(out)]) == 0
-    d = json.load(open(out))
+    with open(out) as fh:
+        d = json.load(fh)
     assert d["w"]["ints_gemm"]["source_hash"] == profsum.kernel_source_hash()
 
 
@@ -68,3 +69,16 @@ def test_mfma_occupancy_and_clock(tmp_path):
     assert abs(e["avg_ms"] - 1.0) < 1e-12
     assert abs(e["clock_ghz"] - 2.4) < 1e-9
     assert abs(e["mfma_busy"] - 0.9) < 1e-12
+
+
+def test_source_hash_ignores_comments_and_spacing():
+    a = {fn: "int f(int x) {\n  return x + 1;  // one\n}\nconst char* s = \"// kept\";\n" for fn in profsum.FRAGMENT_SOURCES}
+    b = {fn: "/* header */\nint f(int x) {\n\n    return x + 1;\n}\nconst char* s = \"// kept\";\n" for fn in profsum.FRAGMENT_SOURCES}
+    c = dict(a)
+    c[profsum.FRAGMENT_SOURCES[0]] = a[profsum.FRAGMENT_SOURCES[0]].replace("x + 1", "x + 2")
+    d = dict(a)
+    d[profsum.FRAGMENT_SOURCES[0]] = a[profsum.FRAGMENT_SOURCES[0]].replace('"// kept"', '"// kepT"')
+    h = profsum.sources_hash
+    assert h(a.get) == h(b.get)
+    assert h(a.get) != h(c.get)          # code changes the hash
+    assert h(a.get) != h(d.get)          # so does a string literal that looks like a comment
