@@ -88,7 +88,11 @@ typedef struct {
                                (screening); must be symmetric */
   int32_t autotune;         /* nonzero: choose each FP64 GEMM's tile shape in situ
                                (rimp2_autotune_report); 0 = fixed shapes */
-  int32_t reserved;
+  int32_t gemm_loader;      /* 0: each FP64 GEMM takes the fastest operand
+                               loader its shape allows; 1: the general loader
+                               only.  Both sum every element in the same order,
+                               so results are bitwise identical; 1 is for
+                               comparison.  Other values: RIMP2_EINVAL. */
 } rimp2_opts;
 
 /* Library version, major*10000 + minor*100 + patch. */

@@ -140,6 +140,7 @@ struct Plan {
   bool gamma, density;
   bool split;                // RIMP2_SPLIT_INT8
   bool autotune;             // in-situ tile choice of the FP64 GEMMs
+  bool general;              // FP64 GEMMs take the general loader only
   int sv, sg;                // digits per operand of (ia|jb) and of Gamma
   int64_t kpv, kpg;          // padded reduction lengths of the split products
   size_t off_dbv, off_ev, off_dbg, off_eg, off_cmax, off_dt, off_et;
@@ -172,6 +173,9 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->nocc = nocc; p->nvir = nvir; p->naux = naux; p->gamma = gamma; p->density = density;
   p->split = o && o->precision == RIMP2_SPLIT_INT8;
   p->autotune = o && o->autotune != 0;
+  if (o && (o->gemm_loader < 0 || o->gemm_loader > 1))
+    return fail(RIMP2_EINVAL, "gemm_loader must be 0 or 1 (got %d)", o->gemm_loader);
+  p->general = o && o->gemm_loader == 1;
   p->sv = (o && o->split_slices) ? o->split_slices : 7;
   p->sg = (o && o->split_slices_gamma) ? o->split_slices_gamma : 5;
   if (p->split && (p->sv < 3 || p->sv > 7 || p->sg < 3 || p->sg > 7))
@@ -260,7 +264,7 @@ int fast_level(const GemmParams& gp, bool nc) {
 int gemm_fast(const GemmParams& gp, bool nc) { return gemm_vec(gp, nc) ? fast_level(gp, nc) : 0; }
 
 template <int BM, int BN, bool NC, int ROLE, bool TRI>
-int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
+int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab, bool general) {
   gp.tiles_m = (int32_t)cdiv(gp.M, BM);
   gp.tiles_n = (int32_t)cdiv(gp.N, BN);
   gp.group_m = 8;
@@ -283,7 +287,7 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab) {
     }
     ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
   }
-  const int fast = gemm_fast(gp, NC);
+  const int fast = general ? 0 : gemm_fast(gp, NC);
   return traced(role, af, ef, ab, st, [&] {
     if (fast == 1)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, 1>), dim3((unsigned)nwg), dim3(256), 0,
@@ -330,22 +334,22 @@ int tile_candidates(int role, const GemmParams& gp, TileShape* c) {
 }
 
 // The GEMM of `role` with square tiles of side bm (one of its candidates).
-int launch_role(int role, int bm, const GemmParams& gp, hipStream_t st, double af, double ab) {
+int launch_role(int role, int bm, const GemmParams& gp, hipStream_t st, double af, double ab, bool general) {
   switch (role) {
     case R_INTS:
-      return bm == 64 ? launch_gemm<64, 64, false, ROLE_INTS, false>(gp, st, role, af, ab)
-                      : launch_gemm<128, 128, false, ROLE_INTS, false>(gp, st, role, af, ab);
+      return bm == 64 ? launch_gemm<64, 64, false, ROLE_INTS, false>(gp, st, role, af, ab, general)
+                      : launch_gemm<128, 128, false, ROLE_INTS, false>(gp, st, role, af, ab, general);
     case R_GAMMA:
-      return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA, false>(gp, st, role, af, ab)
-                      : launch_gemm<128, 128, true, ROLE_GAMMA, false>(gp, st, role, af, ab);
+      return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA, false>(gp, st, role, af, ab, general)
+                      : launch_gemm<128, 128, true, ROLE_GAMMA, false>(gp, st, role, af, ab, general);
     case R_PAB:
-      return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, true>(gp, st, role, af, ab)
-             : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, true>(gp, st, role, af, ab)
-                        : launch_gemm<128, 128, false, ROLE_PAB, true>(gp, st, role, af, ab);
+      return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, true>(gp, st, role, af, ab, general)
+             : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, true>(gp, st, role, af, ab, general)
+                        : launch_gemm<128, 128, false, ROLE_PAB, true>(gp, st, role, af, ab, general);
     case R_PIJ:
-      return bm == 32    ? launch_gemm<32, 32, false, ROLE_PIJ, true>(gp, st, role, af, ab)
-             : bm == 128 ? launch_gemm<128, 128, false, ROLE_PIJ, true>(gp, st, role, af, ab)
-                         : launch_gemm<64, 64, false, ROLE_PIJ, true>(gp, st, role, af, ab);
+      return bm == 32    ? launch_gemm<32, 32, false, ROLE_PIJ, true>(gp, st, role, af, ab, general)
+             : bm == 128 ? launch_gemm<128, 128, false, ROLE_PIJ, true>(gp, st, role, af, ab, general)
+                         : launch_gemm<64, 64, false, ROLE_PIJ, true>(gp, st, role, af, ab, general);
     default:
       return fail(RIMP2_EINVAL, "no GEMM for role %d", role);
   }
@@ -478,14 +482,16 @@ int tuned(const TuneKey& key, int nvar, const TileShape* cand, hipStream_t st, F
 
 // Launches the GEMM of `role`: the default tile shape, or with autotuning the
 // shape's tuned candidate.
-int launch_tuned(int role, const GemmParams& gp, bool autotune, hipStream_t st, double af, double ab) {
+int launch_tuned(int role, const GemmParams& gp, bool autotune, bool general, hipStream_t st, double af, double ab) {
   TileShape c[kTuneVars];
   const int nvar = tile_candidates(role, gp, c);
-  if (!autotune || nvar < 2) return launch_role(role, c[0].bm, gp, st, af, ab);
+  if (!autotune || nvar < 2) return launch_role(role, c[0].bm, gp, st, af, ab, general);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  const TuneKey key{dev, role, gemm_vec(gp, role == R_GAMMA) ? 1 : 0, gp.M, gp.N, gp.K, gp.kchunk};
-  return tuned(key, nvar, c, st, [&](int v) { return launch_role(role, c[v].bm, gp, st, af, ab); });
+  // the key's loader field: 16-byte loads, and whether the fast loaders are allowed
+  const int loader = (gemm_vec(gp, role == R_GAMMA) ? 1 : 0) + (general ? 2 : 0);
+  const TuneKey key{dev, role, loader, gp.M, gp.N, gp.K, gp.kchunk};
+  return tuned(key, nvar, c, st, [&](int v) { return launch_role(role, c[v].bm, gp, st, af, ab, general); });
 }
 
 
@@ -612,7 +618,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
                           gc * nvir, Lc, P.kpv, V, Lc, status, R_INTS8, af,
                           (double)P.sv * (g * v + o * v) * P.kpv + slab, st)))
           return rc;
-      } else if ((rc = launch_tuned(R_INTS, gp, P.autotune, st, af, 8.0 * (g + o) * v * x + slab))) {
+      } else if ((rc = launch_tuned(R_INTS, gp, P.autotune, P.general, st, af, 8.0 * (g + o) * v * x + slab))) {
         return rc;
       }
     }
@@ -651,7 +657,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       } else if (P.s_gam > 1) {
         double* W = (double*)(ws + P.off_gam);
         gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux; gp.status = status;
-        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, st, af, ab))) return rc;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, P.general, st, af, ab))) return rc;
         const int64_t splits = cdiv(L, cdiv(cdiv(L, P.s_gam), kBK) * kBK);
         const int64_t n = gc * nvir * naux;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
@@ -661,7 +667,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
           return rc;
       } else {
         gp.C = out; gp.ldc = naux; gp.split_stride = 0; gp.status = status;
-        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, st, af, ab))) return rc;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, P.general, st, af, ab))) return rc;
       }
     }
     if (P.density) {
@@ -676,7 +682,8 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         double* W = (double*)(ws + P.off_pab);
         gp.C = W; gp.ldc = nvir; gp.split_stride = nvir * nvir; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ab), kBK) * kBK);
-        if ((rc = launch_tuned(R_PAB, gp, P.autotune, st, 2.0 * v * v * g * o * v, 2.0 * slab + 8.0 * splits * v * v)))
+        if ((rc = launch_tuned(R_PAB, gp, P.autotune, P.general, st, 2.0 * v * v * g * o * v,
+                               2.0 * slab + 8.0 * splits * v * v)))
           return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * v * v, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nvir * nvir, 256)), dim3(256), 0, st, Pab,
@@ -695,7 +702,8 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         gp.C = W; gp.ldc = nocc; gp.split_stride = nocc * nocc; gp.status = status;
         const int64_t splits = cdiv(K, cdiv(cdiv(K, P.s_ij), kBK) * kBK);
         // each slab's contribution to P_ij is symmetric: upper-triangular tiles, mirrored
-        if ((rc = launch_tuned(R_PIJ, gp, P.autotune, st, 2.0 * o * o * g * v * v, 2.0 * slab + 8.0 * splits * o * o)))
+        if ((rc = launch_tuned(R_PIJ, gp, P.autotune, P.general, st, 2.0 * o * o * g * v * v,
+                               2.0 * slab + 8.0 * splits * o * o)))
           return rc;
         if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 2) * o * o, st, [&] {
                hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(nocc * nocc, 256)), dim3(256), 0, st, Pij,
@@ -772,9 +780,11 @@ bool kop_vec_rel(const KOperand& o, int64_t K) {
 const int kBatchRole[4] = {R_INTS, R_GAMMA, R_PAB, R_PIJ};
 const int kBatchTile[4][2] = {{128, 64}, {128, 64}, {128, 64}, {64, 32}};
 int glist(int rho, int cand, int loader) { return (rho * 2 + cand) * 4 + loader; }
-// loader of a grouped GEMM (see kGLists); vec: 16-byte loads apply
-int loader_of(const GemmParams& g, bool nc, bool vec) {
+// loader of a grouped GEMM (see kGLists); vec: 16-byte loads apply; general:
+// the general loader only
+int loader_of(const GemmParams& g, bool nc, bool vec, bool general) {
   if (!vec) return 3;
+  if (general) return 2;
   const int f = fast_level(g, nc);
   return f ? f - 1 : 2;
 }
@@ -806,6 +816,9 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
   const bool all_solo = opts && opts->precision == RIMP2_SPLIT_INT8;
   B->d.assign(d, d + nfrag);
   B->autotune = opts && opts->autotune;
+  if (opts && (opts->gemm_loader < 0 || opts->gemm_loader > 1))
+    return fail(RIMP2_EINVAL, "gemm_loader must be 0 or 1 (got %d)", opts->gemm_loader);
+  const bool general = opts && opts->gemm_loader == 1;
   B->plan.resize(nfrag);
   const size_t budget = (opts && opts->slab_budget_bytes) ? opts->slab_budget_bytes : (size_t)64 << 30;
   std::vector<int32_t> order(nfrag), grouped;
@@ -883,7 +896,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       for (int c = 0; c < 2; ++c) {
         GemmParams g = g0;
         const int64_t items = finalize_gemm(g, kBatchTile[rho][c], kBatchTile[rho][c], rho >= 2);
-        GemmList& l = gl[glist(rho, c, loader_of(g, rho == 1, vec))];
+        GemmList& l = gl[glist(rho, c, loader_of(g, rho == 1, vec, general))];
         l.p.push_back(g);
         l.prefix.push_back(l.prefix.back() + items);
       }

@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
         ("slab_budget_bytes", ctypes.c_size_t),
         ("pair_skip", ctypes.c_void_p),
         ("autotune", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("gemm_loader", ctypes.c_int32),
     ]
 
 
@@ -123,9 +123,11 @@ def version() -> int:
 
 
 def make_opts(precision: int = FP64, split_slices: int = 0, slab_group: int = 0, slab_budget_bytes: int = 0,
-              pair_skip: Optional[torch.Tensor] = None, split_slices_gamma: int = 0, autotune: bool = False) -> Opts:
+              pair_skip: Optional[torch.Tensor] = None, split_slices_gamma: int = 0, autotune: bool = False,
+              gemm_loader: int = 0) -> Opts:
     o = Opts()
     o.autotune = 1 if autotune else 0
+    o.gemm_loader = gemm_loader
     o.precision, o.split_slices, o.slab_group = precision, split_slices, slab_group
     o.split_slices_gamma = split_slices_gamma
     o.slab_budget_bytes = slab_budget_bytes

@@ -67,6 +67,7 @@ def test_host_argument_errors():
     assert call(Pij=2048) == rm.RIMP2_EINVAL          # P_ij without P_ab
     assert call(wsb=100) == rm.RIMP2_ENOMEM
     assert call(opts=R.make_opts(precision=7)) == rm.RIMP2_ENOTSUP
+    assert call(opts=R.make_opts(gemm_loader=-1)) == rm.RIMP2_EINVAL
     assert b"P_ij" in R.lib().rimp2_last_error() or True
     assert call(nocc=1 << 21) == rm.RIMP2_EINVAL
 
@@ -104,6 +105,10 @@ def test_batch_plan_errors_and_sizes():
     assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(split), ctypes.byref(n)) == rm.RIMP2_OK
     bad = R.make_opts(precision=9)
     assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(bad), ctypes.byref(n)) == rm.RIMP2_ENOTSUP
+    general = R.make_opts(gemm_loader=1)
+    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(general), ctypes.byref(n)) == rm.RIMP2_OK
+    bad_loader = R.make_opts(gemm_loader=2)
+    assert R.lib().rimp2_batch_workspace_size(2, arr, ctypes.byref(bad_loader), ctypes.byref(n)) == rm.RIMP2_EINVAL
     arr[1].nocc = 0
     assert R.lib().rimp2_batch_workspace_size(2, arr, None, ctypes.byref(n)) == rm.RIMP2_EINVAL
 
