@@ -10,7 +10,7 @@
  * of a fragment: a small network predicts log10|e_ij| from cheap pair
  * features, and pairs predicted below a threshold are skipped by
  * rimp2_fragment (opts->pair_skip).  The full computation stays available as
- * the fallback and as the judge of the screening error.
+ * the fallback and as the reference that measures the screening error.
  */
 #ifndef RIMP2_SCREEN_H
 #define RIMP2_SCREEN_H
