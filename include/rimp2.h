@@ -18,8 +18,9 @@
  * (rimp2_precision).  P_ij and P_ab are formed from their upper triangles and
  * are exactly symmetric.  Results are deterministic: the same inputs and
  * options on the same GPU give bitwise identical outputs (no floating-point
- * atomics; the in-situ autotuner changes tile shapes only, never a summation
- * order).
+ * atomics; the in-situ autotuner changes tile shapes only, and the GEMM
+ * operand loader (opts->gemm_loader) only how operands reach LDS, never a
+ * summation order, so neither changes a result bit).
  *
  * Conventions for every entry point:
  *  - Pointers marked "device" are HIP device pointers; the caller owns every
