@@ -3,7 +3,8 @@
 A step is one pass of the whole path -- (ia|jb) slabs, amplitudes and pair
 energies, E, Gamma, P_ab and P_ij -- over the large synthetic fragment
 (nocc=200, nvir=1800, naux=6000, B = 0.3 N(0,1) exp(-P/1200), seed 1001), with
-every input already resident in HBM.  Prints one JSON line.
+every input already resident in HBM (B is generated on the GPU).  Prints one
+JSON line.
 
   value      algorithmic FP64 TFLOP/s of the whole step: (ia|jb) over unordered
              pairs nocc(nocc+1) nvir^2 naux, Gamma 2 nocc^2 nvir^2 naux,
@@ -11,8 +12,15 @@ every input already resident in HBM.  Prints one JSON line.
   roofline   the dominant kernel's algorithmic rate from HIP events recorded
              around each of its launches on its stream, against the FP64
              MFMA peak (78.6 TFLOP/s)
+  e_gamma_only  the same fragment with P_ij and P_ab off (E, e_ij and Gamma)
   cpu_baseline  the CPU oracle on one occupied slab (k = 0) of the same
              workload, i.e. 1/nocc of the job, timed on this host's cores
+
+A step of the large fragment takes tens of seconds, so the run keeps to a
+wall-clock budget (--budget-s, from process start): the first step is always
+a warmup step, and the timed steps are cut to what fits after it, with room
+kept for the sub-record and the CPU baseline.  ``steps`` and ``warmup`` in the
+line are the counts that ran; ``requested`` holds the ones asked for.
 """
 from __future__ import annotations
 
@@ -23,7 +31,9 @@ import os
 import sys
 import time
 
-import numpy as np
+T_START = time.perf_counter()
+
+import numpy as np  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -67,6 +77,59 @@ def cpu_baseline(B, eo, ev, nocc, alg_total, sample_slabs):
                            "%.3g algorithmic FLOP in %.1f s" % (list(sample_slabs), nocc, flops, dt)}
 
 
+def plan_steps(req_steps: int, req_warmup: int, budget_s: float, elapsed_s: float, step_s: float,
+               reserve_s: float, margin: float = 1.05) -> tuple[int, int]:
+    """Warmup and timed step counts that fit the wall-clock budget.
+
+    Called after the first warmup step has run (it took ``step_s`` and the
+    process has used ``elapsed_s`` so far); ``reserve_s`` is the time kept
+    for the work after the timed steps.  Timed steps come first: at least
+    one, at most ``req_steps``.  Further warmup steps (beyond the one already
+    run) are added only where they fit as well.  Returns (warmup, steps),
+    the warmup count including the step already run."""
+    room = budget_s - elapsed_s - reserve_s
+    fit = int(room // (step_s * margin)) if step_s > 0 else req_steps
+    steps = max(1, min(req_steps, fit))
+    extra = max(0, min(req_warmup - 1, fit - steps))
+    return 1 + extra, steps
+
+
+class Watchdog:
+    """Prints the main record and ends the process if the hard deadline
+    passes while optional extras are still running; without a record it ends
+    the process with status 3.  ``emit`` prints the record exactly once."""
+
+    def __init__(self, t_start: float, deadline_s: float):
+        import threading
+        self.rec = None
+        self._lock = threading.Lock()
+        self._done = False
+        self._timer = threading.Timer(max(1.0, deadline_s - (time.perf_counter() - t_start)), self._fire)
+        self._timer.daemon = True
+        self._timer.start()
+
+    def emit(self, rec: dict) -> bool:
+        with self._lock:
+            if self._done:
+                return False
+            self._done = True
+        self._timer.cancel()
+        sys.stdout.write(json.dumps(rec) + "\n")
+        sys.stdout.flush()
+        return True
+
+    def _fire(self):
+        if self.rec is not None:
+            rec = dict(self.rec)
+            rec["truncated"] = "hard deadline reached: the extras after the timed steps are missing"
+            if self.emit(rec):
+                os._exit(0)
+            return
+        sys.stderr.write("[bench] hard deadline reached before the timed steps finished\n")
+        sys.stderr.flush()
+        os._exit(3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,8 +147,14 @@ def main():
                     help="mbe3: process the fragments in chunks of at most this many GB of B and Gamma, each "
                          "generated on the GPU before it runs (for sets that do not fit in HBM); times the "
                          "batches only")
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps requested (large: capped by --budget-s)")
+    ap.add_argument("--warmup", type=int, default=1, help="warmup steps requested (large: at least one runs)")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="large: wall-clock budget of the whole run from process start; the timed step count "
+                         "is cut to what fits after the first warmup step")
+    ap.add_argument("--deadline-s", type=float, default=0.0,
+                    help="large: hard deadline from process start (0 = budget + 120 s); past it the main record "
+                         "is printed without the extras and the process ends")
     ap.add_argument("--nocc", type=int, default=200)
     ap.add_argument("--nvir", type=int, default=1800)
     ap.add_argument("--naux", type=int, default=6000)
@@ -99,6 +168,7 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true",
                     help="after the timed steps run one FP64 step and report the differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e-gamma", action="store_true", help="large: skip the E+Gamma-only sub-record")
     ap.add_argument("--autotune", action="store_true",
                     help="large: in-situ tile autotuning (the warmup steps take the trials)")
     ap.add_argument("--stats", action="store_true", help="print per-kernel statistics to stderr")
@@ -123,18 +193,27 @@ def main():
         return bench_mbe3(args, torch, synth, rm, dev)
     if args.workload == "screen":
         return bench_screen(args, torch, synth, rm, dev)
+    return bench_large(args, torch, synth, rm, dev)
+
+
+def log(msg: str):
+    print("[bench %6.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+def bench_large(args, torch, synth, rm, dev):
+    """One fragment, every output; see the module docstring."""
+    wd = Watchdog(T_START, args.deadline_s or args.budget_s + 120.0)
     f = synth.Fragment(args.nocc, args.nvir, args.naux, seed=args.seed, decay=args.decay)
     nocc, nvir, naux = f.nocc, f.nvir, f.naux
     large = (nocc, nvir, naux, args.seed, args.decay) == (200, 1800, 6000, 1001, 1200.0)
     workload = "large" if large else "custom"
-    print("[bench] generating inputs nocc=%d nvir=%d naux=%d" % (nocc, nvir, naux), file=sys.stderr, flush=True)
-    B_host = torch.empty((nocc, nvir, naux), dtype=torch.float64, pin_memory=True)
-    f.B(out=B_host.numpy())
+    log("generating inputs on the GPU: nocc=%d nvir=%d naux=%d" % (nocc, nvir, naux))
+    f64 = dict(dtype=torch.float64, device=dev)
+    B = torch.empty((nocc, nvir, naux), **f64)
+    f.B_device(B)
     eo, ev = f.eps()
-    B = B_host.to(dev, non_blocking=True)
     deo = torch.from_numpy(eo).to(dev)
     dev_ = torch.from_numpy(ev).to(dev)
-    f64 = dict(dtype=torch.float64, device=dev)
     E = torch.zeros(2, **f64)
     G = torch.empty((nocc, nvir, naux), **f64)
     Pij = torch.empty((nocc, nocc), **f64)
@@ -144,52 +223,63 @@ def main():
                         precision=rm.SPLIT_INT8 if args.precision == "split" else rm.FP64,
                         split_slices=args.split_slices, split_slices_gamma=args.split_slices_gamma,
                         autotune=args.autotune)
-    ws = torch.empty(rm.workspace_size(nocc, nvir, naux, True, True, opts), dtype=torch.uint8, device=dev)
+    ws_full = rm.workspace_size(nocc, nvir, naux, True, True, opts)
+    ws_eg = 0 if args.no_e_gamma else rm.workspace_size(nocc, nvir, naux, True, False, opts)
+    ws = torch.empty(max(ws_full, ws_eg), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     def step():
         rm.fragment_into(B, deo, dev_, E, G, Pij, Pab, ep, workspace=ws, opts=opts)
 
-    for w in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        print("[bench] warmup step %d done" % w, file=sys.stderr, flush=True)
+    def step_eg():
+        rm.fragment_into(B, deo, dev_, E, G, None, None, ep, workspace=ws, opts=opts)
+
+    # the first step is always a warmup step (the paper discards its first time step)
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    step_s = time.perf_counter() - t0
+    log("warmup step 0: %.2f s" % step_s)
     if rm.read_status(ws) != rm.RIMP2_OK:
         raise SystemExit("device status not OK (orbital-energy gap)")
+    # work kept for after the timed steps: the E+Gamma sub-record (up to two
+    # steps of at most a full step each), the CPU baseline and the copies
+    cpu_est = 0.0 if args.no_cpu_baseline else 20.0 + 3.0e-12 * rm.flops(nocc, nvir, naux)["algorithmic"] / nocc
+    reserve = (0.0 if args.no_e_gamma else 2.0 * step_s) + cpu_est + 15.0
+    if args.compare_fp64:
+        reserve += 1.2 * step_s
+    warmup, steps = plan_steps(args.steps, args.warmup, args.budget_s, time.perf_counter() - T_START, step_s,
+                               reserve)
+    log("plan: %d timed step(s), %d warmup step(s) (requested %d and %d, budget %.0f s, reserve %.0f s)"
+        % (steps, warmup, args.steps, args.warmup, args.budget_s, reserve))
+    for w in range(1, warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % w)
 
     rm.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = rm.timing_collect()
     rm.timing_enable(False)
+    log("timed %d step(s) in %.3f s" % (steps, t1 - t0))
+    E_full = E.cpu().numpy().copy()
+    ep0_full = ep[0].cpu().numpy().copy()
+    G0_full = G[0].cpu().numpy().copy()
     if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        src = torch.ones(1 << 27, **f64)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print("[bench] timed %d step(s) in %.3f s" % (args.steps, t1 - t0), file=sys.stderr, flush=True)
-    # adjacent step, outside the timed region: the metric contraction of Gamma
-    # with a synthetic symmetric J^{-1/2} stand-in
-    from paper_2410_21888_amd import gradient as GR
-    q = torch.arange(naux, dtype=torch.float64, device=dev)
-    Jm = torch.exp(-(q[:, None] - q[None, :]).abs() / 50.0) * 0.01 + torch.eye(naux, **f64)
-    Gm = torch.empty_like(G)
-    GR.gamma_metric(G, Jm, Gm)
-    torch.cuda.synchronize()
-    tg = time.perf_counter()
-    GR.gamma_metric(G, Jm, Gm)
-    torch.cuda.synchronize()
-    tg = time.perf_counter() - tg
-    del Gm, Jm
 
     fl = rm.flops(nocc, nvir, naux)
-    dt = (t1 - t0) / args.steps
+    dt = (t1 - t0) / steps
     value = fl["algorithmic"] / dt / 1e12
     dom = max(stats, key=lambda s: s["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
@@ -197,20 +287,15 @@ def main():
     executed = dom["exec_flops"] / (dom["total_ms"] / 1e3) / 1e12
     traffic = measured_traffic(dom["name"], workload)
     if args.stats:
-        for s in sorted(stats, key=lambda s: -s["total_ms"]):
-            print("[bench] %-14s launches=%5d total=%10.2f ms avg=%9.3f ms alg=%7.2f TF/s exec=%7.2f TF/s "
-                  "alg_bytes/s=%8.1f GB/s" % (s["name"], s["launches"], s["total_ms"], s["total_ms"] / s["launches"],
-                                              s["alg_flops"] / s["total_ms"] / 1e9,
-                                              s["exec_flops"] / s["total_ms"] / 1e9,
-                                              s["alg_bytes"] / s["total_ms"] / 1e6), file=sys.stderr)
+        print_stats(stats)
 
     out = {
         "metric": METRIC,
         "value": round(value, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -220,7 +305,9 @@ def main():
         "config": {"workload": "%s fragment nocc=%d nvir=%d naux=%d" % (workload, nocc, nvir, naux),
                    "nocc": nocc, "nvir": nvir, "naux": naux, "seed": args.seed, "aux_decay": args.decay,
                    "outputs": "E, e_ij, Gamma, P_ij, P_ab", "flops_counted": "algorithmic E+Gamma+P_ab+P_ij",
-                   "slab_group": args.slab_group or "auto", "autotune": bool(args.autotune)},
+                   "slab_group": args.slab_group or "auto", "autotune": bool(args.autotune),
+                   "inputs": "B generated on the GPU (seeded counter-based normals), resident in HBM"},
+        "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
         "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4),
         "tflops_executed": round(sum(s["exec_flops"] for s in stats) / (t1 - t0) / 1e12, 4),
         "roofline": {"bound": "mfma", "kernel": dom["name"], "achieved": round(achieved, 4),
@@ -229,9 +316,9 @@ def main():
                      "alg_flops_per_launch": dom["alg_flops"] / dom["launches"],
                      "traffic": traffic,
                      "executed_tflops": round(executed, 4), "frac_executed": round(executed / FP64_PEAK_TFLOPS, 4)},
-        "E_hi": float(E[0]), "E_lo": float(E[1]),
-        "gamma_metric": {"ms": round(tg * 1e3, 3), "tflops": round(2.0 * nocc * nvir * naux * naux / tg / 1e12, 3),
-                         "note": "Gamma J^-1/2 with a synthetic metric, outside the timed step"},
+        "kernels": {s["name"]: {"launches": s["launches"], "ms": round(s["total_ms"] / steps, 2)}
+                    for s in sorted(stats, key=lambda s: -s["total_ms"])},
+        "E_hi": float(E_full[0]), "E_lo": float(E_full[1]),
     }
     if dom["name"] == "ints_gemm":
         out["roofline"]["note"] = ("the (ia|jb) GEMM computes ordered pairs (twice the symmetric algorithmic count) "
@@ -245,17 +332,20 @@ def main():
         out["config"]["precision"] = "split-int8 ints=%d gamma=%d digits" % (args.split_slices or 7,
                                                                              args.split_slices_gamma or 5)
         out["roofline"]["note"] = "FP64-equivalent rate of the split kernel against the FP64 peak"
-    if args.compare_fp64:
-        import math
+    wd.rec = out
+
+    def left():
+        return args.budget_s - (time.perf_counter() - T_START)
+
+    if args.compare_fp64 and left() > 1.2 * step_s + cpu_est:
         G_s, ep_s, Pij_s, Pab_s, E_s = G.clone(), ep.clone(), Pij.clone(), Pab.clone(), E.clone()
-        del ws
-        torch.cuda.empty_cache()
         o64 = rm.make_opts(slab_group=args.slab_group)
         ws64 = torch.empty(rm.workspace_size(nocc, nvir, naux, True, True, o64), dtype=torch.uint8, device=dev)
         t2 = time.perf_counter()
         rm.fragment_into(B, deo, dev_, E, G, Pij, Pab, ep, workspace=ws64, opts=o64)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        del ws64
         e64 = E.cpu().numpy()
         es = E_s.cpu().numpy()
         rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
@@ -265,17 +355,73 @@ def main():
             "e_pair_rel_fro": rel(ep_s, ep), "fp64_step_s": t3 - t2,
             "speedup_vs_fp64": (t3 - t2) / dt,
         }
-    if not args.no_cpu_baseline:
-        B_np = B_host.numpy()
+        del G_s, ep_s, Pij_s, Pab_s, E_s
+        log("FP64 comparison step: %.2f s" % (t3 - t2))
+
+    # E + Gamma only (the metric's own pair of outputs): same fragment, P off
+    eg = None
+    if not args.no_e_gamma and left() > step_s + cpu_est:
+        fl_eg = rm.flops(nocc, nvir, naux, gamma=True, density=False)
+        eg_warm = 0
+        t2 = time.perf_counter()
+        step_eg()
+        torch.cuda.synchronize()
+        eg_first = time.perf_counter() - t2
+        if left() > eg_first * 1.05 + cpu_est:
+            eg_warm = 1
+            rm.timing_enable(True)
+            t2 = time.perf_counter()
+            step_eg()
+            torch.cuda.synchronize()
+            eg_s = time.perf_counter() - t2
+            st_eg = rm.timing_collect()
+            rm.timing_enable(False)
+        else:
+            eg_s, st_eg = eg_first, []
+        E_eg = E.cpu().numpy().copy()
+        eg = {"value": round(fl_eg["algorithmic"] / eg_s / 1e12, 4), "unit": "TFLOP/s",
+              "ms_per_step": round(eg_s * 1e3, 3), "steps": 1, "warmup": eg_warm,
+              "frac_fp64_peak": round(fl_eg["algorithmic"] / eg_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+              "flops_counted": "algorithmic E+Gamma", "outputs": "E, e_ij, Gamma",
+              "E_hi": float(E_eg[0]), "E_lo": float(E_eg[1]),
+              "abs_dE_vs_full_step_Eh": abs(math.fsum([float(E_eg[0]), float(E_eg[1]), -float(E_full[0]),
+                                                       -float(E_full[1])]))}
+        if st_eg:
+            eg["kernels"] = {s["name"]: {"launches": s["launches"], "ms": round(s["total_ms"], 2)}
+                             for s in sorted(st_eg, key=lambda s: -s["total_ms"])}
+        ep0_eg = ep[0].cpu().numpy().copy()
+        G0_eg = G[0].cpu().numpy().copy()
+        out["e_gamma_only"] = eg
+        log("E+Gamma-only step: %.2f s (%.2f TFLOP/s)" % (eg_s, eg["value"]))
+
+    if not args.no_cpu_baseline and left() > cpu_est * 0.5:
+        B_np = B.cpu().numpy()
         ref, cb = cpu_baseline(B_np, eo, ev, nocc, fl["algorithmic"], [0])
         out["cpu_baseline"] = cb
-        g_ep = ep[0].cpu().numpy()
-        g_G0 = G[0].cpu().numpy()
-        out["sampled_parity"] = {
-            "e_pair_row0_max_rel": float(np.max(np.abs(g_ep - ref["e_pair"][0]) / np.abs(ref["e_pair"][0]))),
-            "gamma_row0_rel_fro": float(np.linalg.norm(g_G0 - ref["Gamma"][0]) / np.linalg.norm(ref["Gamma"][0])),
-        }
-    print(json.dumps(out))
+        sp = {"e_pair_row0_max_rel": float(np.max(np.abs(ep0_full - ref["e_pair"][0]) / np.abs(ref["e_pair"][0]))),
+              "gamma_row0_rel_fro": float(np.linalg.norm(G0_full - ref["Gamma"][0]) /
+                                          np.linalg.norm(ref["Gamma"][0])),
+              "gamma_row0_max_abs_over_max": float(np.max(np.abs(G0_full - ref["Gamma"][0])) /
+                                                   np.max(np.abs(ref["Gamma"][0])))}
+        if eg is not None:
+            sp["e_gamma_only"] = {
+                "e_pair_row0_max_rel": float(np.max(np.abs(ep0_eg - ref["e_pair"][0]) / np.abs(ref["e_pair"][0]))),
+                "gamma_row0_rel_fro": float(np.linalg.norm(G0_eg - ref["Gamma"][0]) /
+                                            np.linalg.norm(ref["Gamma"][0]))}
+        out["sampled_parity"] = sp
+        del B_np
+        log("CPU baseline: %.3f TFLOP/s on %d cores" % (cb["value"], cb["cores"]))
+    out["wall_s"] = round(time.perf_counter() - T_START, 1)
+    wd.emit(out)
+
+
+def print_stats(stats):
+    for s in sorted(stats, key=lambda s: -s["total_ms"]):
+        print("[bench] %-14s launches=%5d total=%10.2f ms avg=%9.3f ms alg=%7.2f TF/s exec=%7.2f TF/s "
+              "alg_bytes/s=%8.1f GB/s" % (s["name"], s["launches"], s["total_ms"], s["total_ms"] / s["launches"],
+                                          s["alg_flops"] / s["total_ms"] / 1e9,
+                                          s["exec_flops"] / s["total_ms"] / 1e9,
+                                          s["alg_bytes"] / s["total_ms"] / 1e6), file=sys.stderr)
 
 
 def bench_mbe3(args, torch, synth, rm, dev):
