@@ -88,7 +88,7 @@ def exact_sum(values) -> tuple[float, float]:
     return hi, lo
 
 
-def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True, slabs=None) -> dict:
+def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True, slabs=None, skip=None) -> dict:
     """All outputs of the fragment kernel.
 
     Returns a dict with
@@ -101,6 +101,10 @@ def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True, slab
     ``slabs`` (an iterable of k) restricts the loop to those k: then e_pair
     rows and Gamma rows k are complete, the other rows stay zero, P_ij and P_ab
     hold only those slabs' contributions and E sums the computed rows.
+    ``skip`` ([nocc][nocc], or None) screens occupied pairs out: a nonzero
+    skip[k, j] or skip[j, k] removes the unordered pair {k, j}, which then has
+    no amplitudes (X_kj = T_kj = 0 in both orders) and e_kj = 0.  This is the
+    pair screening the learned model drives; the mask names unordered pairs.
     """
     B = np.asarray(B)
     nocc, nvir, naux = B.shape
@@ -110,9 +114,11 @@ def fragment(B, eps_occ, eps_vir, gamma: bool = True, density: bool = True, slab
     P_ij = np.zeros((nocc, nocc), dtype=dt) if density else None
     P_ab = np.zeros((nvir, nvir), dtype=dt) if density else None
     for k in (range(nocc) if slabs is None else slabs):
-        X_k = np.empty((nocc, nvir, nvir), dtype=dt)
-        T_k = np.empty((nocc, nvir, nvir), dtype=dt)
+        X_k = np.zeros((nocc, nvir, nvir), dtype=dt)
+        T_k = np.zeros((nocc, nvir, nvir), dtype=dt)
         for j in range(nocc):
+            if skip is not None and (skip[k][j] or skip[j][k]):
+                continue            # screened out: X_kj = T_kj = 0, e_kj = 0
             V, X, T = pair_quantities(B, eps_occ, eps_vir, k, j)
             X_k[j], T_k[j] = X, T
             e_pair[k, j] = np.sum(T * V)
@@ -157,6 +163,22 @@ def gamma_row(B, eps_occ, eps_vir, i: int, a: int) -> np.ndarray:
         D_row = denominators(eps_occ[i], eps_occ[j], eps_vir)[a]
         T_row = 2.0 * row / D_row - col / D_row   # D_ij is symmetric in (a, b)
         out = out + T_row @ Bj
+    return out
+
+
+def gamma_rows(B, eps_occ, eps_vir, i: int, rows) -> np.ndarray:
+    """Gamma[i, a, :] for every a in ``rows`` ([len(rows)][naux]), as
+    gamma_row computes one, with a single pass over the rows of B."""
+    rows = np.asarray(list(rows), dtype=np.int64)
+    nocc = len(eps_occ)
+    out = 0.0
+    for j in range(nocc):
+        Bj = B[j]
+        V_row = B[i][rows] @ Bj.T   # V_ij[a, b] for a in rows
+        V_col = Bj[rows] @ B[i].T   # V_ij[b, a] for a in rows (indexed [a][b])
+        D = denominators(eps_occ[i], eps_occ[j], eps_vir)[rows]
+        T = 2.0 * V_row / D - V_col / D
+        out = out + T @ Bj
     return out
 
 

@@ -17,7 +17,10 @@ Facts used (derivations are in the docstrings):
 * dE/d eps_i = 2 (P_ij)_ii and dE/d eps_a = 2 (P_ab)_aa, complex step;
 * symmetry, trace and sign properties, orthogonal rotation of the auxiliary
   index, global shift of all orbital energies, scaling of B, zero padding and
-  index permutation.
+  index permutation;
+* pair screening: screening out every pair that contains occupied orbital i
+  gives the results of the fragment with orbital i deleted (zero in row and
+  column i), and a mask names unordered pairs.
 """
 from __future__ import annotations
 
@@ -275,8 +278,8 @@ def pin_permutation(O):
 
 
 def pin_sampled_entry_points(O):
-    """The single-output functions (pair_energy, gamma_row, p_ab_element,
-    p_ij_element) agree with brute force."""
+    """The single-output functions (pair_energy, gamma_row, gamma_rows,
+    p_ab_element, p_ij_element) agree with brute force."""
     B, eo, ev = tiny_inputs(3, 4, 5, 111)
     bf = brute_force(B, eo, ev)
     for i in range(3):
@@ -286,6 +289,7 @@ def pin_sampled_entry_points(O):
     for i in range(3):
         for a in range(4):
             assert rel(O.gamma_row(B, eo, ev, i, a), bf["Gamma"][i, a]) <= 1e-12
+        assert rel(O.gamma_rows(B, eo, ev, i, [3, 0, 2]), bf["Gamma"][i, [3, 0, 2]]) <= 1e-12
     for a in range(4):
         for b in range(4):
             assert abs(O.p_ab_element(B, eo, ev, a, b) - bf["P_ab"][a, b]) <= 1e-12 * abs(bf["P_ab"]).max()
@@ -322,3 +326,51 @@ ALL_PINS = [pin_brute_force, pin_closed_form_single_pair, pin_equal_energies, pi
             pin_dE_deps_is_2_diagP, pin_symmetry_and_sign, pin_aux_rotation, pin_global_shift,
             pin_scaling, pin_zero_padding, pin_permutation, pin_sampled_entry_points, pin_exact_sum,
             pin_gamma_metric_is_three_centre_derivative]
+
+
+def pin_skip_all_pairs_of_an_orbital_deletes_it(O):
+    """Screening out every pair {i, j} that contains occupied orbital i (the
+    diagonal pair included) leaves exactly the fragment without orbital i:
+    E and the other e_jk, Gamma rows and P_ij entries not involving i, and
+    P_ab equal the oracle run on B and eps_occ with orbital i removed; row i
+    of Gamma and row and column i of e_pair and P_ij are zero.  A mask that
+    marks only row i names the same unordered pairs as one that marks row
+    and column i."""
+    nocc, nvir, naux = 4, 3, 5
+    B, eo, ev = tiny_inputs(nocc, nvir, naux, 21)
+    for i in (0, 2, nocc - 1):
+        keep = [k for k in range(nocc) if k != i]
+        red = O.fragment(B[keep], eo[keep], ev)
+        for half in (False, True):
+            skip = np.zeros((nocc, nocc), dtype=np.uint8)
+            skip[i, :] = 1          # row i alone names every pair {i, j}
+            if not half:
+                skip[:, i] = 1
+            got = O.fragment(B, eo, ev, skip=skip)
+            assert abs(got["E_hi"] - red["E_hi"]) <= RTOL * abs(red["E_hi"])
+            assert rel(got["e_pair"][np.ix_(keep, keep)], red["e_pair"]) <= RTOL
+            assert np.all(got["e_pair"][i, :] == 0) and np.all(got["e_pair"][:, i] == 0)
+            assert rel(got["Gamma"][keep], red["Gamma"]) <= RTOL
+            assert np.all(got["Gamma"][i] == 0)
+            assert rel(got["P_ij"][np.ix_(keep, keep)], red["P_ij"]) <= RTOL
+            assert np.all(got["P_ij"][i, :] == 0) and np.all(got["P_ij"][:, i] == 0)
+            assert rel(got["P_ab"], red["P_ab"]) <= RTOL
+
+
+def pin_skip_nothing_is_the_full_result(O):
+    """An all-zero mask screens nothing out: every output is the unscreened
+    one, bit for bit; a mask over one pair zeroes exactly e_ij and e_ji."""
+    B, eo, ev = tiny_inputs(3, 4, 5, 22)
+    full = O.fragment(B, eo, ev)
+    got = O.fragment(B, eo, ev, skip=np.zeros((3, 3), dtype=np.uint8))
+    for key in ("e_pair", "Gamma", "P_ij", "P_ab"):
+        assert np.array_equal(got[key], full[key])
+    skip = np.zeros((3, 3), dtype=np.uint8)
+    skip[2, 0] = 1
+    one = O.fragment(B, eo, ev, skip=skip)
+    ref = full["e_pair"].copy()
+    ref[0, 2] = ref[2, 0] = 0.0
+    assert np.array_equal(one["e_pair"], ref)
+
+
+ALL_PINS.extend([pin_skip_all_pairs_of_an_orbital_deletes_it, pin_skip_nothing_is_the_full_result])

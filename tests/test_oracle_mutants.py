@@ -30,7 +30,7 @@ MUTANTS = [
     ("amplitude multiplies", "return V_ij / D_ij", "return V_ij * D_ij"),
     ("energy uses X for T", "e_pair[k, j] = np.sum(T * V)", "e_pair[k, j] = np.sum(X * V)"),
     ("energy factor 2", "e_pair[k, j] = np.sum(T * V)", "e_pair[k, j] = np.sum(2.0 * T * V)"),
-    ("pair loop misses j = 0", "for j in range(nocc):\n            V, X, T", "for j in range(1, nocc):\n            V, X, T"),
+    ("pair loop misses j = 0", "for j in range(nocc):\n            if skip", "for j in range(1, nocc):\n            if skip"),
     ("Gamma uses X for T", "Gamma[k] += T @ B[j]", "Gamma[k] += X @ B[j]"),
     ("Gamma transposed T", "Gamma[k] += T @ B[j]", "Gamma[k] += T.T @ B[j]"),
     ("Gamma wrong B row", "Gamma[k] += T @ B[j]", "Gamma[k] += T @ B[k]"),
@@ -44,6 +44,10 @@ MUTANTS = [
     ("p_ij_element sign", "    return -s\n", "    return s\n"),
     ("gamma_metric transposed", "return Gamma @ Jm.T", "return Gamma @ Jm"),
     ("gamma_metric drops the metric", "return Gamma @ Jm.T", "return Gamma"),
+    ("gamma_rows exchange from row", "T = 2.0 * V_row / D - V_col / D", "T = 2.0 * V_row / D - V_row / D"),
+    ("gamma_rows wrong exchange index", "V_col = Bj[rows] @ B[i].T", "V_col = B[i][rows] @ Bj.T"),
+    ("skip mask read one way only", "(skip[k][j] or skip[j][k])", "skip[k][j]"),
+    ("skipped pair still computed", "continue            # screened out", "pass            # screened out"),
     ("pair_energy uses X", "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * V)",
      "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * X)"),
 ]

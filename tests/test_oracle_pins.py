@@ -4,7 +4,8 @@ Pin status of every oracle function:
   pair_integrals, denominators, amplitudes, combination, pair_quantities,
   fragment (all outputs)      brute force, closed form, equal energies,
                               dE/dB = 4 Gamma, dE/d eps = 2 diag P, invariants
-  pair_energy, gamma_row, p_ab_element, p_ij_element
+  fragment(skip=...)          deleting an orbital, empty mask
+  pair_energy, gamma_row, gamma_rows, p_ab_element, p_ij_element
                               brute force
   exact_sum                   exact cancellation cases
 No function is unpinned.
