@@ -11,7 +11,7 @@ import torch
 import synth
 from oracle import rimp2_oracle as O
 import paper_2410_21888_amd as rm
-from gpu_util import to_dev, rel_fro, energy_error, say
+from gpu_util import to_dev, rel_fro, energy_error, say, assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +32,8 @@ def test_autotune_bitwise_and_decides():
     orc = O.fragment(B, eo, ev)
     assert energy_error(ref.E, orc["E_hi"], orc["E_lo"]) <= 1e-12 * abs(orc["E_hi"])
     assert rel_fro(ref.Gamma.cpu().numpy(), orc["Gamma"]) <= 1e-13
+    for key in ("Gamma", "P_ij", "P_ab"):
+        assert_elementwise(getattr(ref, key).cpu().numpy(), orc[key], 1e-12, 1e-12, key)
     rm.autotune_reset()
     opts = rm.make_opts(slab_group=2, autotune=True)
     for call in range(8):

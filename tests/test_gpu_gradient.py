@@ -1,6 +1,7 @@
 """Metric contraction of Gamma on the GPU (rimp2_gamma_metric) against the
-oracle, element by element; the metric is not symmetric, so a transposed
-operand would show."""
+oracle, element by element (|d| <= 1e-12 |ref| + 1e-12 max|ref row|) and by
+relative Frobenius norm; the metric is not symmetric, so a transposed operand
+would show."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +10,7 @@ import synth
 from oracle import rimp2_oracle as O
 import paper_2410_21888_amd as rm
 from paper_2410_21888_amd import gradient as G
-from gpu_util import to_dev, rel_fro, say
+from gpu_util import to_dev, rel_fro, say, assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +25,9 @@ def test_gamma_metric_matches_oracle(shape):
     dG, dJ = to_dev(Gam, Jm)
     got = G.gamma_metric(dG, dJ).cpu().numpy()
     torch.cuda.synchronize()
-    assert rel_fro(got, O.gamma_metric(Gam, Jm)) <= 1e-13
+    ref = O.gamma_metric(Gam, Jm)
+    assert rel_fro(got, ref) <= 1e-13
+    assert_elementwise(got, ref, 1e-12, 1e-12, "gamma_metric")
 
 
 def test_gamma_metric_after_the_fragment_kernel():
@@ -35,6 +38,7 @@ def test_gamma_metric_after_the_fragment_kernel():
     got = G.gamma_metric(r.Gamma, to_dev(Jm)[0]).cpu().numpy()
     ref = O.gamma_metric(O.fragment(B, eo, ev, density=False)["Gamma"], Jm)
     assert rel_fro(got, ref) <= 1e-13
+    assert_elementwise(got, ref, 1e-12, 1e-12, "gamma_metric")
 
 
 def test_gamma_metric_rejects_overlap():

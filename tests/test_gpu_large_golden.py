@@ -4,7 +4,11 @@ occupied orbitals, every output), against the CPU oracle's stored outputs.
 
 tests/golden/large_oracle.npz was written by tests/golden/make_large_golden.py,
 which calls only oracle/ and synth/ (about 1.7 h on 6 cores).  Gamma is not
-stored; its rows are checked one by one with oracle.gamma_row.
+stored; its rows are computed here with oracle.gamma_rows, at every tile edge
+of the virtual index (a = 0, 127, 128, 1799 against 128-wide GEMM tiles) for
+occupied orbitals at the edges of the slab groups of 6 (k = 0, 5, 6) and in
+the last, ragged group (k = 198, 199), plus two interior ones.  Every element
+is held to |d| <= 1e-12 |ref| + 1e-12 max|ref row|.
 """
 import math
 import os
@@ -16,7 +20,7 @@ import torch
 import synth
 from oracle import rimp2_oracle as O
 import paper_2410_21888_amd as rm
-from gpu_util import rel_fro, say
+from gpu_util import rel_fro, say, assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -47,15 +51,19 @@ def test_large_fragment_against_stored_oracle():
     assert np.all(np.abs(ep - ref_ep) <= 1e-12 * np.abs(ref_ep) + 1e-15)
     pij = r.P_ij.cpu().numpy()
     assert rel_fro(pij, g["P_ij"]) <= 1e-12
+    assert_elementwise(pij, g["P_ij"], 1e-12, 1e-12, "P_ij")
     pab = r.P_ab.cpu().numpy()
     rows = g["P_ab_row_index"]
     assert rel_fro(pab[rows], g["P_ab_rows"]) <= 1e-12
+    assert_elementwise(pab[rows], g["P_ab_rows"], 1e-12, 1e-12, "P_ab rows")
     assert rel_fro(np.diag(pab), g["P_ab_diag"]) <= 1e-12
     assert abs(np.linalg.norm(pab) - float(g["P_ab_fro"])) <= 1e-12 * float(g["P_ab_fro"])
     del dB
-    for i, a in ((0, 0), (57, 900), (120, 3), (199, 1799)):
-        got = r.Gamma[i, a].cpu().numpy()
-        ref = O.gamma_row(B, eo, ev, i, a)
+    avals = [0, 127, 128, 900, 1799]
+    for i in (0, 5, 6, 57, 120, 198, 199):
+        got = r.Gamma[i, avals].cpu().numpy()
+        ref = O.gamma_rows(B, eo, ev, i, avals)
         err = rel_fro(got, ref)
-        say("large golden: Gamma[%d, %d, :] rel err %.2e" % (i, a, err))
+        say("large golden: Gamma[%d, %s, :] rel err %.2e" % (i, avals, err))
         assert err <= 1e-12
+        assert_elementwise(got, ref, 1e-12, 1e-12, "Gamma[%d]" % i)

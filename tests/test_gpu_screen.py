@@ -10,7 +10,7 @@ from oracle import rimp2_oracle as O
 from oracle import screen_oracle as S
 import paper_2410_21888_amd as rm
 from paper_2410_21888_amd import screen as SC
-from gpu_util import to_dev, rel_fro, say
+from gpu_util import to_dev, rel_fro, say, assert_elementwise
 import pins
 
 pytestmark = pytest.mark.gpu
@@ -86,24 +86,72 @@ def test_energy_only_symmetric_path(shape, g):
     assert abs(math.fsum([e[0], e[1], -ref["E_hi"], -ref["E_lo"]])) <= 1e-12 * abs(ref["E_hi"])
 
 
-@pytest.mark.parametrize("density", [False, True])
-def test_pair_skip_sums_unskipped_pairs(density):
-    f = synth.screen_system(4001, nocc=10, nvir=40, naux=80)
+# The screened path against the oracle with the same mask (oracle.fragment's
+# skip): every element of e_pair, Gamma, P_ij and P_ab.  Slab groups of 3 put
+# skipped pairs both inside one group (blocks formed from their mirror) and
+# across groups (blocks formed on their own); slab_group=0 puts every pair in
+# one group; density=False with gamma=False takes the energy-only path.
+@pytest.mark.parametrize("outputs,g", [("energy", 3), ("gamma", 3), ("all", 3), ("all", 0), ("all", 1)])
+def test_pair_skip_matches_oracle_with_mask(outputs, g):
+    nocc = 10
+    f = synth.screen_system(4001, nocc=nocc, nvir=40, naux=80)
     B, eo, ev = f.arrays()
-    ref = O.fragment(B, eo, ev, gamma=False, density=False)
+    gamma, density = outputs in ("gamma", "all"), outputs == "all"
     rng = np.random.default_rng(8)
-    m = np.triu(rng.random((10, 10)) < 0.4, 1)
+    m = np.triu(rng.random((nocc, nocc)) < 0.4, 1)
+    m[2, 3] = m[0, 9] = True        # one pair inside the first group, one across groups
     m = (m | m.T).astype(np.uint8)
+    ref = O.fragment(B, eo, ev, gamma=gamma, density=density, skip=m)
     dB, deo, dev_ = to_dev(B, eo, ev)
-    skip = torch.from_numpy(m).to(DEV)
-    r = rm.fragment(dB, deo, dev_, gamma=density, density=density, opts=rm.make_opts(pair_skip=skip, slab_group=3))
+    say("pair skip: outputs=%s slab_group=%d skipped pairs=%d" % (outputs, g, int(m.sum()) // 2))
+    r = rm.fragment(dB, deo, dev_, gamma=gamma, density=density,
+                    opts=rm.make_opts(pair_skip=torch.from_numpy(m).to(DEV), slab_group=g))
     ep = r.e_pair.cpu().numpy()
     assert np.all(ep[m > 0] == 0)
-    keep = m == 0
-    assert np.all(np.abs(ep[keep] - ref["e_pair"][keep]) <= 1e-12 * np.abs(ref["e_pair"][keep]))
+    assert_elementwise(ep, ref["e_pair"], 1e-12, 1e-15, "e_pair")
     e = r.E.cpu().numpy()
-    want = math.fsum(ref["e_pair"][keep].tolist())
-    assert abs(math.fsum([e[0], e[1], -want])) <= 1e-12 * abs(want)
+    assert abs(math.fsum([e[0], e[1], -ref["E_hi"], -ref["E_lo"]])) <= 1e-12 * abs(ref["E_hi"])
+    if gamma:
+        G = r.Gamma.cpu().numpy()
+        assert_elementwise(G, ref["Gamma"], 1e-12, 1e-12, "Gamma")
+    if density:
+        assert_elementwise(r.P_ij.cpu().numpy(), ref["P_ij"], 1e-12, 1e-12, "P_ij")
+        assert_elementwise(r.P_ab.cpu().numpy(), ref["P_ab"], 1e-12, 1e-12, "P_ab")
+
+
+@pytest.mark.parametrize("outputs", ["energy", "all"])
+def test_pair_skip_mask_names_unordered_pairs(outputs):
+    """A mask with only (i, j) or only (j, i) set screens the pair out in
+    both orders: bitwise the same outputs as the symmetric mask, whatever the
+    slab grouping, and equal to the oracle."""
+    nocc = 9
+    f = synth.screen_system(4002, nocc=nocc, nvir=36, naux=72)
+    B, eo, ev = f.arrays()
+    gamma = density = outputs == "all"
+    rng = np.random.default_rng(10)
+    up = np.triu(rng.random((nocc, nocc)) < 0.35, 1)
+    sym = (up | up.T).astype(np.uint8)
+    # each pair marked on one side only, the side chosen at random
+    side = rng.random((nocc, nocc)) < 0.5
+    asym = np.zeros_like(sym)
+    asym[up & side] = 1
+    asym[(up & ~side).T] = 1
+    dB, deo, dev_ = to_dev(B, eo, ev)
+    ref = O.fragment(B, eo, ev, gamma=gamma, density=density, skip=sym)
+    for g in (1, 4, 0):
+        outs = []
+        for mask in (sym, asym):
+            r = rm.fragment(dB, deo, dev_, gamma=gamma, density=density,
+                            opts=rm.make_opts(pair_skip=torch.from_numpy(mask).to(DEV), slab_group=g))
+            outs.append(r)
+        for name, a, b in zip(outs[0]._fields, outs[0], outs[1]):
+            if a is not None:
+                assert torch.equal(a, b), (g, name)
+        assert_elementwise(outs[1].e_pair.cpu().numpy(), ref["e_pair"], 1e-12, 1e-15, "e_pair")
+        if gamma:
+            assert_elementwise(outs[1].Gamma.cpu().numpy(), ref["Gamma"], 1e-12, 1e-12, "Gamma")
+            assert_elementwise(outs[1].P_ab.cpu().numpy(), ref["P_ab"], 1e-12, 1e-12, "P_ab")
+            assert_elementwise(outs[1].P_ij.cpu().numpy(), ref["P_ij"], 1e-12, 1e-12, "P_ij")
 
 
 def test_training_reduces_loss():

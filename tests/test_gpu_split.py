@@ -2,8 +2,9 @@
 
 Bar: |dE| <= 1 uEh (exact evaluation of the (hi, lo) pairs) and relative
 Frobenius error <= 1e-8 for Gamma, P_ij and P_ab, with the default digit
-counts (7 for (ia|jb), 5 for Gamma).  The error must also fall steeply with
-the number of digits (about 2^-7 per digit).
+counts (7 for (ia|jb), 5 for Gamma); every element of Gamma, P_ij, P_ab and
+e_pair is also held to |d| <= 1e-8 |ref| + 1e-8 max|ref row|.  The error must
+also fall steeply with the number of digits (about 2^-7 per digit).
 """
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ import torch
 import synth
 from oracle import rimp2_oracle as O
 import paper_2410_21888_amd as rm
-from gpu_util import to_dev, rel_fro, energy_error, say
+from gpu_util import to_dev, rel_fro, energy_error, say, assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +30,10 @@ def check(f, opts, e_tol=1e-6, rel_tol=1e-8):
     dE = energy_error(r.E, ref["E_hi"], ref["E_lo"])
     assert dE <= e_tol, dE
     for key, got in (("Gamma", r.Gamma), ("P_ij", r.P_ij), ("P_ab", r.P_ab), ("e_pair", r.e_pair)):
-        err = rel_fro(got.cpu().numpy(), ref[key])
+        g = got.cpu().numpy()
+        err = rel_fro(g, ref[key])
         assert err <= rel_tol, (key, err)
+        assert_elementwise(g, ref[key], rel_tol, rel_tol, key)
     return dE
 
 
