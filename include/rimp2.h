@@ -84,9 +84,11 @@ typedef struct {
                                3..7 (0 = 5) */
   size_t  slab_budget_bytes;/* cap on the slab part of the workspace when
                                slab_group == 0; 0 = 64 GiB */
-  const uint8_t* pair_skip; /* device [nocc][nocc] or NULL: nonzero (i,j) marks
-                               an occupied pair whose (ia|jb) block is skipped
-                               (screening); must be symmetric */
+  const uint8_t* pair_skip; /* device [nocc][nocc] or NULL: a nonzero (i,j) or
+                               (j,i) marks the unordered occupied pair {i,j}
+                               as screened out: its (ia|jb) blocks are not
+                               formed, e_ij = e_ji = 0, and X_ij = T_ij = 0 in
+                               Gamma and P (screening) */
   int32_t autotune;         /* nonzero: choose each FP64 GEMM's tile shape in situ
                                (rimp2_autotune_report); 0 = fixed shapes */
   int32_t gemm_loader;      /* 0: each FP64 GEMM takes the fastest operand

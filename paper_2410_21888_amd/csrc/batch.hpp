@@ -58,7 +58,7 @@ __global__ void relocate_tables_kernel(char* base, GemmParams* gp, int ngp, AmpD
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ngp) {
     GemmParams& p = gp[i];
-    reloc_t(p.A.base, base); reloc_t(p.Bk.base, base); reloc_t(p.Bn.base, base);
+    reloc_t(p.A.base, base); reloc_t(p.Am.base, base); reloc_t(p.Bk.base, base); reloc_t(p.Bn.base, base);
     reloc_t(p.C, base); reloc_t(p.status, base);
   }
   if (i < namp) {

@@ -5,6 +5,9 @@
 //   Gamma          G[(k,a), P]     = sum_(j,b) T[(k,a), (j,b)] B[(j,b), P] (B N-contiguous)
 //   P_ab           sum_(k,j,c) T(a, (k,j,c)) X(b, (k,j,c))                (B K-contiguous)
 //   P_ij           sum_(k,a,b) T(i, (k,a,b)) X(j, (k,a,b))                (B K-contiguous)
+//   Gamma, transposed blocks (symmetric pair path)
+//                  G[(j,b), P]    += sum_(k,a) T[(k,a), (j,b)] B[(k,a), P]
+//                                 (A M-contiguous, B N-contiguous)
 // The slab operands store the reduction index in two levels (runs of kdiv
 // contiguous elements, runs ks1 apart), which the loaders follow directly so
 // no operand is ever copied or transposed in HBM.
@@ -54,16 +57,20 @@ struct GemmParams {
   int64_t M, N, K;
   int64_t kchunk;       // reduction length per split (multiple of BK)
   int32_t tiles_m, tiles_n, splits, group_m;
-  KOperand A;
+  KOperand A;           // A when K-contiguous
+  NOperand Am;          // A when M-contiguous: element (m, k) at Am.base[k * Am.ld + m]
   KOperand Bk;          // B when K-contiguous
   NOperand Bn;          // B when N-contiguous
   double* C;            // split z writes C + z * split_stride
   int64_t ldc;
   int64_t split_stride;
+  int32_t accumulate;   // nonzero: C += A B instead of C = A B (no split-K)
   const int32_t* status;  // nonzero: do nothing
   // Optional pair screening of an (ia|jb) slab: row m belongs to occupied
   // orbital skip_k0 + m / skip_nvir, column n to skip_j0 + n / skip_nvir; a
-  // tile whose pairs are all marked in skip[k * skip_nocc + j] is not computed.
+  // tile whose pairs are all screened out is not computed.  A pair {k, j} is
+  // screened out when skip[k * skip_nocc + j] or skip[j * skip_nocc + k] is
+  // nonzero (the mask names unordered pairs).
   const uint8_t* skip;
   int32_t skip_nvir, skip_k0, skip_j0, skip_nocc;
   // pair_upper (same row/column to pair mapping): a tile all of whose pairs
@@ -85,7 +92,9 @@ __device__ __forceinline__ bool tile_screened(const GemmParams& p, int tm, int t
   const int64_t j_lo = n0 / p.skip_nvir, j_hi = (min(p.N, n0 + BN) - 1) / p.skip_nvir;
   for (int64_t k = k_lo; k <= k_hi; ++k)
     for (int64_t j = j_lo; j <= j_hi; ++j)
-      if (p.skip[(p.skip_k0 + k) * p.skip_nocc + p.skip_j0 + j] == 0) return false;
+      if (p.skip[(p.skip_k0 + k) * p.skip_nocc + p.skip_j0 + j] == 0 &&
+          p.skip[(p.skip_j0 + j) * p.skip_nocc + p.skip_k0 + k] == 0)
+        return false;
   return true;
 }
 
@@ -97,8 +106,9 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
   return x * q + (x < rem ? x : rem) + (w >> 3);
 }
 
-// ROLE only gives each contraction its own kernel symbol (profiler names).
-enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3 };
+// ROLE gives each contraction its own kernel symbol (profiler names);
+// ROLE_GAMMA_T also selects the M-contiguous A loader.
+enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3, ROLE_GAMMA_T = 4 };
 
 // Decodes logical tile index t (< tiles of one split) into (tm, tn):
 // triangular order (TRI) or groups of group_m m-tiles.
@@ -135,7 +145,9 @@ struct GemmLds {
 
 // One output tile (tm, tn) of split z.  Ends with a workgroup barrier, so the
 // LDS can be reused by the next tile.
-template <int BM, int BN, int BK, bool B_NCONTIG, bool VEC, bool TRI, int FAST>
+// A_MC: A is M-contiguous (p.Am) and is loaded like an N-contiguous B, two
+// consecutive rows m per 16-byte load, into the same k-major LDS layout.
+template <int BM, int BN, int BK, bool B_NCONTIG, bool VEC, bool TRI, int FAST, bool A_MC = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, int z, GemmLds<BM, BN, BK>& lds) {
   static_assert(BM % 32 == 0 && BN % 32 == 0 && BK % 8 == 0, "tile shape");
   typedef double d2 __attribute__((ext_vector_type(2)));
@@ -151,6 +163,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
   constexpr int BNN = B_NCONTIG ? BK / NSTEP : 1;
   static_assert(!B_NCONTIG || (256 % NP == 0 && BK % NSTEP == 0), "N loader shape");
   constexpr int BREG = B_NCONTIG ? BNN : BKN;
+  constexpr int MP = BM / 2;                   // row pairs per k row (M-contiguous A loader)
+  constexpr int MSTEP = 256 / MP;              // k rows per pass
+  constexpr int AMN = A_MC ? BK / MSTEP : 1;
+  static_assert(!A_MC || (256 % MP == 0 && BK % MSTEP == 0), "M loader shape");
+  constexpr int AREG = A_MC ? AMN : AN;
 
   auto& As = lds.a;
   auto& Bs = lds.b;
@@ -165,14 +182,16 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
 
   // K-contiguous loaders: thread -> rows r0 + s*RSTEP, reduction pair (kk, kk+1)
   const int kk = 2 * (tid % KP), r0 = tid / KP;
-  int64_t aq, ar, bq = 0, br = 0;
-  { const int64_t k = kbeg + kk; aq = k / p.A.kdiv; ar = k - aq * p.A.kdiv; }
+  int64_t aq = 0, ar = 0, bq = 0, br = 0;
+  if (!A_MC) { const int64_t k = kbeg + kk; aq = k / p.A.kdiv; ar = k - aq * p.A.kdiv; }
   if (!B_NCONTIG) { const int64_t k = kbeg + kk; bq = k / p.Bk.kdiv; br = k - bq * p.Bk.kdiv; }
   // N-contiguous loader: thread -> column pair nn, k rows kn0 + s*NSTEP
   const int nn = 2 * (tid % NP), kn0 = tid / NP;
+  // M-contiguous A loader: thread -> row pair mm, k rows km0 + s*MSTEP
+  const int mm = 2 * (tid % MP), km0 = tid / MP;
   const bool fullA = (m0 + BM <= p.M), fullB = (n0 + BN <= p.N);
 
-  d2 ra[AN], rb[BREG];
+  d2 ra[AREG], rb[BREG];
 
   // One K-contiguous operand tile: element (row, k) = base[row*rs + (k/kdiv)*ks1 + k%kdiv].
   // (q, r) is this thread's position for k = kc + kk.  With VEC the host has
@@ -202,7 +221,27 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
   auto load_chunk = [&](int c) {
     const int64_t kc = kbeg + (int64_t)c * BK;
     const bool fullk = (kc + BK <= kend);
-    RIMP2_KLOAD(p.A, m0, p.M, fullA, aq, ar, ra, AN)
+    if constexpr (!A_MC) {
+      RIMP2_KLOAD(p.A, m0, p.M, fullA, aq, ar, ra, AN)
+    } else {
+      const int64_t m = m0 + mm;
+      if (VEC && fullA && fullk) {
+        const double* src = p.Am.base + (kc + km0) * p.Am.ld + m;
+        const int64_t st = (int64_t)MSTEP * p.Am.ld;
+#pragma unroll
+        for (int s = 0; s < AMN; ++s) ra[s] = *(const d2*)(src + s * st);
+      } else {
+#pragma unroll
+        for (int s = 0; s < AMN; ++s) {
+          const int64_t k = kc + km0 + s * MSTEP;
+          const double* row = p.Am.base + min(k, kend - 1) * p.Am.ld;
+          const double x0 = (k < kend && m < p.M) ? row[m] : 0.0;
+          const double x1 = (k < kend && m + 1 < p.M) ? row[m + 1] : 0.0;
+          ra[s][0] = x0;
+          ra[s][1] = x1;
+        }
+      }
+    }
     if (!B_NCONTIG) {
       RIMP2_KLOAD(p.Bk, n0, p.N, fullB, bq, br, rb, BKN)
     } else {
@@ -224,19 +263,26 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
         }
       }
     }
-    ar += BK;
-    while (ar >= p.A.kdiv) { ar -= p.A.kdiv; ++aq; }
+    if (!A_MC) {
+      ar += BK;
+      while (ar >= p.A.kdiv) { ar -= p.A.kdiv; ++aq; }
+    }
     if (!B_NCONTIG) {
       br += BK;
       while (br >= p.Bk.kdiv) { br -= p.Bk.kdiv; ++bq; }
     }
   };
 #undef RIMP2_KLOAD
-  auto store_from = [&](int buf, const d2 (&sa)[AN], const d2 (&sb)[BREG]) {
+  auto store_from = [&](int buf, const d2 (&sa)[AREG], const d2 (&sb)[BREG]) {
+    if (!A_MC) {
 #pragma unroll
-    for (int s = 0; s < AN; ++s) {
-      As[buf][kk * LDA + r0 + s * RSTEP] = sa[s][0];
-      As[buf][(kk + 1) * LDA + r0 + s * RSTEP] = sa[s][1];
+      for (int s = 0; s < AREG; ++s) {
+        As[buf][kk * LDA + r0 + s * RSTEP] = sa[s][0];
+        As[buf][(kk + 1) * LDA + r0 + s * RSTEP] = sa[s][1];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < AREG; ++s) *(d2*)&As[buf][(km0 + s * MSTEP) * LDA + mm] = sa[s];
     }
     if (!B_NCONTIG) {
 #pragma unroll
@@ -281,17 +327,24 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
   if constexpr (FAST > 0) {
     const int nfull = (int)((kend - kbeg) / BK);
     if (nfull > 0) {
-      d2 xa[2][AN], xb[2][BREG];
+      d2 xa[2][AREG], xb[2][BREG];
       // start of the next chunk to load (uniform): offset of each K operand
       // and its position in the current run
       int64_t oa = 0, pa = 0, ob = 0, pb = 0;
-      { const int64_t q = kbeg / p.A.kdiv; pa = kbeg - q * p.A.kdiv; oa = q * p.A.ks1 + pa; }
+      if (!A_MC) { const int64_t q = kbeg / p.A.kdiv; pa = kbeg - q * p.A.kdiv; oa = q * p.A.ks1 + pa; }
+      else { oa = kbeg * p.Am.ld; }
       if (!B_NCONTIG) { const int64_t q = kbeg / p.Bk.kdiv; pb = kbeg - q * p.Bk.kdiv; ob = q * p.Bk.ks1 + pb; }
       else { ob = kbeg * p.Bn.ld; }
       int nload = 0;
-      const double* ap[AN];
+      const double* ap[AREG];
+      if (!A_MC) {
 #pragma unroll
-      for (int s = 0; s < AN; ++s) ap[s] = p.A.base + min(m0 + r0 + s * RSTEP, p.M - 1) * p.A.rs + kk;
+        for (int s = 0; s < AREG; ++s) ap[s] = p.A.base + min(m0 + r0 + s * RSTEP, p.M - 1) * p.A.rs + kk;
+      } else {
+        const int64_t m = min(m0 + mm, p.M - 2);   // M is even here
+#pragma unroll
+        for (int s = 0; s < AREG; ++s) ap[s] = p.Am.base + (int64_t)(km0 + s * MSTEP) * p.Am.ld + m;
+      }
       const double* bp[BREG];
       if (!B_NCONTIG) {
 #pragma unroll
@@ -305,16 +358,20 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
       auto wrap = [&](const KOperand& o, int64_t pos) -> int64_t {
         return (FAST == 2 && pos + kk >= o.kdiv) ? o.ks1 - o.kdiv : 0;
       };
-      auto fload = [&](d2 (&da)[AN], d2 (&db)[BREG]) {
-        const int64_t xa_ = oa + wrap(p.A, pa);
+      auto fload = [&](d2 (&da)[AREG], d2 (&db)[BREG]) {
+        const int64_t xa_ = A_MC ? oa : oa + wrap(p.A, pa);
 #pragma unroll
-        for (int s = 0; s < AN; ++s) da[s] = *(const d2*)(ap[s] + xa_);
+        for (int s = 0; s < AREG; ++s) da[s] = *(const d2*)(ap[s] + xa_);
         const int64_t xb_ = B_NCONTIG ? ob : ob + wrap(p.Bk, pb);
 #pragma unroll
         for (int s = 0; s < BREG; ++s) db[s] = *(const d2*)(bp[s] + xb_);
         if (++nload < nfull) {
-          oa += BK; pa += BK;
-          if (pa >= p.A.kdiv) { pa -= p.A.kdiv; oa += p.A.ks1 - p.A.kdiv; }
+          if (A_MC) {
+            oa += (int64_t)BK * p.Am.ld;
+          } else {
+            oa += BK; pa += BK;
+            if (pa >= p.A.kdiv) { pa -= p.A.kdiv; oa += p.A.ks1 - p.A.kdiv; }
+          }
           if (B_NCONTIG) {
             ob += (int64_t)BK * p.Bn.ld;
           } else {
@@ -356,14 +413,21 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
       // the ragged last chunk: per-element masks (pairs, as the reduction length is even)
       const int64_t kt = kbeg + (int64_t)nfull * BK;
       const d2 zero = {0.0, 0.0};
-      {
+      if (!A_MC) {
         const int64_t k = kt + kk;
         const bool in = k < kend;
         const int64_t q = in ? k / p.A.kdiv : 0;
         const int64_t off = in ? q * p.A.ks1 + (k - q * p.A.kdiv) : 0;
 #pragma unroll
-        for (int s = 0; s < AN; ++s)
+        for (int s = 0; s < AREG; ++s)
           ra[s] = in ? *(const d2*)(p.A.base + min(m0 + r0 + s * RSTEP, p.M - 1) * p.A.rs + off) : zero;
+      } else {
+        const int64_t m = min(m0 + mm, p.M - 2);
+#pragma unroll
+        for (int s = 0; s < AREG; ++s) {
+          const int64_t k = kt + km0 + s * MSTEP;
+          ra[s] = k < kend ? *(const d2*)(p.Am.base + k * p.Am.ld + m) : zero;
+        }
       }
       if (!B_NCONTIG) {
         const int64_t k = kt + kk;
@@ -429,7 +493,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams& p, int tm, int tn, i
         const int64_t n = n0 + wn * WTN + j * 16 + (lane & 15);
         if (m < p.M && n < p.N) {
           if (!TRI) {
-            C[m * p.ldc + n] = acc[i][j][r];
+            if (p.accumulate) C[m * p.ldc + n] += acc[i][j][r];
+            else C[m * p.ldc + n] = acc[i][j][r];
           } else if (m <= n) {   // every lower element is the mirror of an upper one
             C[m * p.ldc + n] = acc[i][j][r];
             if (m < n) C[n * p.ldc + m] = acc[i][j][r];
@@ -450,7 +515,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
   int tm, tn;
   decode_tile<TRI>(p, wl - z * ntiles, tm, tn);
   if (tile_screened<BM, BN>(p, tm, tn)) return;
-  gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, FAST>(p, tm, tn, z, lds);
+  gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, FAST, ROLE == ROLE_GAMMA_T>(p, tm, tn, z, lds);
 }
 
 // Persistent grouped launch over many independent GEMMs (one per fragment):

@@ -122,8 +122,9 @@ __device__ __forceinline__ void put_pair_energy(double sh, double sl, double* e_
 
 constexpr int AT = 32;
 
-// Pair (k, j > k) of a slab group k0.. that holds every column (j0 = 0,
-// ncols = nocc) and both rows k and j, whose block (j, k) was not computed:
+// Pair (k, j > k) of a slab group k0.. whose slab holds both rows k and j
+// and both columns k and j (columns j0 .. j0+ncols-1, j0 <= k), and whose
+// block (j, k) was not computed:
 // V_jk is V_kj transposed, and D_jk = D_kj, so this workgroup forms both
 // pairs from V_kj alone.  For positions (a, b) and (b, a) of the block:
 //   X_kj[a,b] = V_kj[a,b] / D[a,b]    X_kj[b,a] = V_kj[b,a] / D[b,a]
@@ -134,14 +135,14 @@ constexpr int AT = 32;
 // workgroup covers tile pairs [q0, q1) of the block.  VP and VQ are two
 // AT x (AT+1) LDS tiles of the caller.
 __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab, const double* eo, const double* ev,
-                                                       int nocc, int nvir, bool skip, double* e_pair, int k0, int k,
-                                                       int j, int q0, int q1, double* epart, double (*VP)[AT + 1],
-                                                       double (*VQ)[AT + 1]) {
-  const int64_t ld = (int64_t)nocc * nvir;
-  double* bkj = S + ((int64_t)(k - k0) * nvir * nocc + j) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
-  double* bjk = S + ((int64_t)(j - k0) * nvir * nocc + k) * nvir;
-  double* tkj = Tslab + ((int64_t)(k - k0) * nvir * nocc + j) * nvir;
-  double* tjk = Tslab + ((int64_t)(j - k0) * nvir * nocc + k) * nvir;
+                                                       int nocc, int nvir, bool skip, double* e_pair, int k0, int j0,
+                                                       int ncols, int k, int j, int q0, int q1, double* epart,
+                                                       double (*VP)[AT + 1], double (*VQ)[AT + 1]) {
+  const int64_t ld = (int64_t)ncols * nvir;
+  double* bkj = S + ((int64_t)(k - k0) * nvir * ncols + (j - j0)) * nvir;  // element (a,b) of pair (k,j) at bkj[a*ld + b]
+  double* bjk = S + ((int64_t)(j - k0) * nvir * ncols + (k - j0)) * nvir;
+  double* tkj = Tslab + ((int64_t)(k - k0) * nvir * ncols + (j - j0)) * nvir;
+  double* tjk = Tslab + ((int64_t)(j - k0) * nvir * ncols + (k - j0)) * nvir;
   const double ekj = eo[k] + eo[j];
   const int t = threadIdx.x, tc = t & 31, tr0 = t >> 5;
   const int nt = (nvir + AT - 1) / AT;
@@ -220,10 +221,16 @@ __device__ __forceinline__ void amplitude_mirror_block(double* S, double* Tslab,
 // (ia|jb) GEMM has not computed the blocks j < k of those pairs, which are
 // left to their mirror, and pairs j > k form both blocks
 // (amplitude_mirror_block; with energy_only as sym = 1).  Other pairs are
-// formed on their own.  A screened pair (pair_skip, may be null) writes
-// e = 0 (and, unless energy_only, zero X and T) without reading V.
+// formed on their own.
+// sym = 3 (Gamma without P, slab holding j >= k0 only): pairs inside the
+// group as with sym = 2 (both blocks from the block j > k); a pair with j
+// past the group forms its own block only (its transpose block T_jk = T_kj^T
+// is never formed: the transposed Gamma GEMM reads T_kj instead), and e_kj is
+// written to both e_kj and e_jk.
+// A screened pair (pair_skip, may be null) writes e = 0 (and, unless
+// energy_only, zero X and T) without reading V.
 __device__ __forceinline__ bool pair_mirrored(int sym, int k0, int g, int j) {
-  return sym == 1 || (sym == 2 && j >= k0 && j < k0 + g);
+  return sym == 1 || sym == 3 || (sym == 2 && j >= k0 && j < k0 + g);
 }
 
 __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const double* eo, const double* ev, int nocc,
@@ -238,11 +245,13 @@ __device__ __forceinline__ void amplitude_block(double* S, double* Tslab, const 
   const int64_t ld = (int64_t)ncols * nvir;
   double* blk = S + ((int64_t)kk * nvir * ncols + jj) * nvir;  // element (a,b) at blk[a*ld + b]
   double* tblk = Tslab + ((int64_t)kk * nvir * ncols + jj) * nvir;
-  const bool skip = pair_skip != nullptr && pair_skip[(int64_t)k * nocc + j] != 0;
+  // the mask names unordered pairs: either entry screens the pair out
+  const bool skip = pair_skip != nullptr &&
+                    (pair_skip[(int64_t)k * nocc + j] != 0 || pair_skip[(int64_t)j * nocc + k] != 0);
   const int nt = (nvir + AT - 1) / AT, npt = nt * (nt + 1) / 2;
   const int q0 = (int)((int64_t)npt * w / W), q1 = (int)((int64_t)npt * (w + 1) / W);
-  if (sym == 2 && paired && !energy_only && j > k) {
-    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k0, k, j, q0, q1, epart, XP, XQ);
+  if ((sym == 2 || sym == 3) && j >= k0 && j < k0 + g && !energy_only && j > k) {
+    amplitude_mirror_block(S, Tslab, eo, ev, nocc, nvir, skip, e_pair, k0, j0, ncols, k, j, q0, q1, epart, XP, XQ);
     return;
   }
   if (skip && energy_only) {

@@ -44,10 +44,11 @@ namespace {
 
 // ---- kernel timing -------------------------------------------------------
 enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
-            R_NROLES };
+            R_GAMMA_T, R_NROLES };
 const char* const kRoleName[R_NROLES] = {"gap_check",  "ints_gemm",     "amplitude",  "gamma_gemm",
                                          "pab_gemm",   "pij_gemm",      "splitk_reduce", "energy_sum",
-                                         "status_copy", "digit_split", "ints_oz8",   "gamma_oz8"};
+                                         "status_copy", "digit_split", "ints_oz8",   "gamma_oz8",
+                                         "gamma_t_gemm"};
 struct TraceRec {
   int role;
   hipEvent_t e0, e1;
@@ -138,6 +139,9 @@ bool pab_tile96(int64_t nvir) {
 struct Plan {
   int64_t nocc, nvir, naux;
   bool gamma, density;
+  bool sym;                  // Gamma without P (FP64): (ia|jb) over pairs j >= k only
+  bool g_fixed;              // slab_group given by the caller
+  double budget;             // slab budget in bytes (slab_group == 0)
   bool split;                // RIMP2_SPLIT_INT8
   bool autotune;             // in-situ tile choice of the FP64 GEMMs
   bool general;              // FP64 GEMMs take the general loader only
@@ -157,6 +161,25 @@ int64_t amp_splits(int64_t pairs, int64_t nvir) {
   const int64_t nt = (nvir + 31) / 32, npt = nt * (nt + 1) / 2;
   const int64_t w = (6144 + pairs - 1) / pairs;
   return std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(w, kAmpSplitMax), npt));
+}
+
+// Occupied orbitals in the slab group that starts at k0.  The ordered path
+// uses one size g for every group.  The symmetric path's slabs hold the
+// columns j >= k0 only, so without a caller-given size each group takes the
+// most orbitals whose two slabs fit the budget, and later groups grow.
+int64_t group_at(const Plan& P, int64_t k0) {
+  if (!P.sym || P.g_fixed) return std::min<int64_t>(P.g, P.nocc - k0);
+  const double per_k = 2.0 * 8.0 * (double)(P.nocc - k0) * P.nvir * P.nvir;
+  // at most as many rows as one reduction launch covers (its grid counts
+  // work-items in 32 bits)
+  const int64_t red = std::max<int64_t>(1, kMaxWorkgroups * 256 / (P.nvir * P.naux));
+  return std::max<int64_t>(1, std::min<int64_t>({(int64_t)(P.budget / per_k), P.nocc - k0, red}));
+}
+
+// Split-K factor of the symmetric path's Gamma GEMM over the row blocks of a
+// group of gc orbitals starting at k0 (reduction over the pairs j >= k0).
+int64_t sym_gamma_splits(const Plan& P, int64_t k0, int64_t gc) {
+  return choose_splits(cdiv(gc * P.nvir, kTile) * cdiv(P.naux, kTile), (P.nocc - k0) * P.nvir);
 }
 
 // grouped: the fragment runs in a batch wave (whole slab, no split amplitude
@@ -184,12 +207,14 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->kpg = cdiv(nocc * nvir, 64) * 64;
   const bool need_T = gamma || density;
   const double slab_per_k = (need_T ? 2.0 : 1.0) * 8.0 * (double)nocc * nvir * nvir;
+  p->sym = gamma && !density && !p->split && !grouped;
+  p->g_fixed = o && o->slab_group > 0;
+  p->budget = (o && o->slab_budget_bytes) ? (double)o->slab_budget_bytes : 64.0 * (1ull << 30);
   int64_t g;
-  if (o && o->slab_group > 0) {
+  if (p->g_fixed) {
     g = std::min<int64_t>(o->slab_group, nocc);
   } else {
-    const double budget = (o && o->slab_budget_bytes) ? (double)o->slab_budget_bytes : 64.0 * (1ull << 30);
-    g = (int64_t)(budget / slab_per_k);
+    g = (int64_t)(p->budget / slab_per_k);
     g = std::max<int64_t>(1, std::min<int64_t>(g, nocc));
   }
   p->g = g;
@@ -198,22 +223,37 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->s_ab = density ? choose_splits(tab * (tab + 1) / 2, g * nocc * nvir) : 0;
   p->s_ij = density ? choose_splits(tij * (tij + 1) / 2, g * nvir * nvir) : 0;
   p->s_gam = gamma ? choose_splits(cdiv(g * nvir, kTile) * cdiv(naux, kTile), nocc * nvir) : 0;
+  // slab elements (g x ncols pair blocks) and Gamma split partials of the
+  // largest group
+  double slab_elems = (double)g * nocc * nvir * nvir, gam_part = (double)p->s_gam * g * nvir * naux;
+  if (p->sym) {
+    slab_elems = gam_part = 0.0;
+    for (int64_t k0 = 0; k0 < nocc;) {
+      const int64_t gc = group_at(*p, k0), s = sym_gamma_splits(*p, k0, gc);
+      slab_elems = std::max(slab_elems, (double)gc * (nocc - k0) * nvir * nvir);
+      if (s > 1) gam_part = std::max(gam_part, (double)s * gc * nvir * naux);
+      k0 += gc;
+    }
+  }
   size_t off = 0;
   p->off_status = off; off = align_up(off + 64);
-  p->off_V = off; off = align_up(off + (size_t)(8.0 * g * nocc * nvir * nvir));
-  p->off_T = off; if (need_T) off = align_up(off + (size_t)(8.0 * g * nocc * nvir * nvir));
+  p->off_V = off; off = align_up(off + (size_t)(8.0 * slab_elems));
+  p->off_T = off; if (need_T) off = align_up(off + (size_t)(8.0 * slab_elems));
   p->off_e = off; off = align_up(off + 8 * (size_t)nocc * nocc);
   p->off_pab = off; if (density) off = align_up(off + 8 * (size_t)p->s_ab * nvir * nvir);
   p->off_pij = off; if (density) off = align_up(off + 8 * (size_t)p->s_ij * nocc * nocc);
-  p->off_gam = off; if (gamma && p->s_gam > 1 && !p->split) off = align_up(off + 8 * (size_t)p->s_gam * g * nvir * naux);
+  p->off_gam = off;
+  if (gamma && !p->split && (p->sym || p->s_gam > 1)) off = align_up(off + (size_t)(8.0 * gam_part));
   p->off_epart = off;
   if (!grouped) {  // largest partial array of the amplitude launches (see run_fragment)
     const bool eonly = !(gamma || density);
     int64_t most = 0;
-    for (int64_t k0 = 0; k0 < nocc; k0 += g) {
-      const int64_t pairs = std::min<int64_t>(g, nocc - k0) * (eonly ? nocc - k0 : nocc);
+    for (int64_t k0 = 0; k0 < nocc;) {
+      const int64_t gc = group_at(*p, k0);
+      const int64_t pairs = gc * ((eonly || p->sym) ? nocc - k0 : nocc);
       const int64_t W = amp_splits(pairs, nvir);
       if (W > 1) most = std::max(most, pairs * W);
+      k0 += gc;
     }
     off = align_up(off + 16 * (size_t)most);
   }
@@ -232,7 +272,8 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   }
   p->total = off;
   int rc;
-  if (gamma && p->s_gam > 1 && (rc = check_grid(cdiv(g * nvir * naux, 256), "reduction"))) return rc;
+  if (gamma && p->s_gam > 1 && !p->sym && (rc = check_grid(cdiv(g * nvir * naux, 256), "reduction"))) return rc;
+  if (p->sym && p->g_fixed && (rc = check_grid(cdiv(g * nvir * naux, 256), "reduction"))) return rc;
   if (p->split && ((rc = check_grid(nocc * nvir, "digit split")) || (rc = check_grid(cdiv(p->kpg, 32), "digit split"))))
     return rc;
   return RIMP2_OK;
@@ -245,23 +286,30 @@ bool kop_vec(const KOperand& o, int64_t K) {
   return (uintptr_t)o.base % 16 == 0 && o.rs % 2 == 0 && (plain || (o.kdiv % 2 == 0 && o.ks1 % 2 == 0));
 }
 
-// 16-byte loads for a whole GEMM (the split length is a multiple of kBK, so even).
-bool gemm_vec(const GemmParams& gp, bool nc) {
-  return kop_vec(gp.A, gp.K) && (nc ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
+// 16-byte loads for a whole GEMM (the split length is a multiple of kBK, so
+// even).  amc: A is M-contiguous (pairs of rows, like an N-contiguous B).
+bool gemm_vec(const GemmParams& gp, bool nc, bool amc = false) {
+  const bool a = amc ? ((uintptr_t)gp.Am.base % 16 == 0 && gp.Am.ld % 2 == 0) : kop_vec(gp.A, gp.K);
+  return a && (nc ? ((uintptr_t)gp.Bn.base % 16 == 0 && gp.Bn.ld % 2 == 0) : kop_vec(gp.Bk, gp.K));
 }
 
 // The kernels' FAST path (returns 0 when it does not apply): 16-byte loads,
 // an even reduction length (no reduction pair straddles the end), runs of the
 // K operands at least one chunk long (a chunk crosses at most one run
 // boundary) and an even N for an N-contiguous B (its column pairs past the
-// edge are read at N - 2).  2 when a K operand's runs can end inside a chunk.
-int fast_level(const GemmParams& gp, bool nc) {
+// edge are read at N - 2; likewise an even M for an M-contiguous A).  2 when
+// a K operand's runs can end inside a chunk.
+int fast_level(const GemmParams& gp, bool nc, bool amc = false) {
   auto runs = [&](const KOperand& o) { return o.kdiv >= gp.K || o.kdiv >= kBK; };
   auto wraps = [&](const KOperand& o) { return o.kdiv < gp.K && o.kdiv % kBK != 0; };
-  if (!(gp.K % 2 == 0 && gp.kchunk % kBK == 0 && runs(gp.A) && (nc ? gp.N % 2 == 0 : runs(gp.Bk)))) return 0;
-  return (wraps(gp.A) || (!nc && wraps(gp.Bk))) ? 2 : 1;
+  if (!(gp.K % 2 == 0 && gp.kchunk % kBK == 0 && (amc ? gp.M % 2 == 0 : runs(gp.A)) &&
+        (nc ? gp.N % 2 == 0 : runs(gp.Bk))))
+    return 0;
+  return ((!amc && wraps(gp.A)) || (!nc && wraps(gp.Bk))) ? 2 : 1;
 }
-int gemm_fast(const GemmParams& gp, bool nc) { return gemm_vec(gp, nc) ? fast_level(gp, nc) : 0; }
+int gemm_fast(const GemmParams& gp, bool nc, bool amc = false) {
+  return gemm_vec(gp, nc, amc) ? fast_level(gp, nc, amc) : 0;
+}
 
 template <int BM, int BN, bool NC, int ROLE, bool TRI>
 int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab, bool general) {
@@ -275,7 +323,10 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab, b
   const int64_t tiles = TRI ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
   const int64_t nwg = tiles * gp.splits;
   if (int rc = check_grid(nwg, "GEMM")) return rc;
-  const bool vec = gemm_vec(gp, NC);
+  constexpr bool AMC = ROLE == ROLE_GAMMA_T;
+  if (AMC && gp.splits != 1) return fail(RIMP2_EINVAL, "M-contiguous GEMM without split-K only");
+  if (gp.accumulate && (TRI || gp.splits != 1)) return fail(RIMP2_EINVAL, "accumulating GEMM without split-K only");
+  const bool vec = gemm_vec(gp, NC, AMC);
   double ef = (TRI ? 0.5 * (1.0 + 1.0 / gp.tiles_m) : 1.0) * 2.0 * (double)gp.M * gp.N * gp.K;
   if (gp.pair_upper) {  // tiles not skipped: those with a pair j >= k or j < pair_lo (see tile_screened)
     int64_t kept = 0;
@@ -287,7 +338,7 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab, b
     }
     ef *= (double)kept / ((double)gp.tiles_m * gp.tiles_n);
   }
-  const int fast = general ? 0 : gemm_fast(gp, NC);
+  const int fast = general ? 0 : gemm_fast(gp, NC, AMC);
   return traced(role, af, ef, ab, st, [&] {
     if (fast == 1)
       hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, kBK, NC, ROLE, true, TRI, 1>), dim3((unsigned)nwg), dim3(256), 0,
@@ -316,6 +367,7 @@ int tile_candidates(int role, const GemmParams& gp, TileShape* c) {
   switch (role) {
     case R_INTS:
     case R_GAMMA:
+    case R_GAMMA_T:
       c[0] = {128, 128}; c[1] = {64, 64};
       return 2;
     case R_PAB: {
@@ -342,6 +394,9 @@ int launch_role(int role, int bm, const GemmParams& gp, hipStream_t st, double a
     case R_GAMMA:
       return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA, false>(gp, st, role, af, ab, general)
                       : launch_gemm<128, 128, true, ROLE_GAMMA, false>(gp, st, role, af, ab, general);
+    case R_GAMMA_T:
+      return bm == 64 ? launch_gemm<64, 64, true, ROLE_GAMMA_T, false>(gp, st, role, af, ab, general)
+                      : launch_gemm<128, 128, true, ROLE_GAMMA_T, false>(gp, st, role, af, ab, general);
     case R_PAB:
       return bm == 64   ? launch_gemm<64, 64, false, ROLE_PAB, true>(gp, st, role, af, ab, general)
              : bm == 96 ? launch_gemm<96, 96, false, ROLE_PAB, true>(gp, st, role, af, ab, general)
@@ -489,7 +544,7 @@ int launch_tuned(int role, const GemmParams& gp, bool autotune, bool general, hi
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   // the key's loader field: 16-byte loads, and whether the fast loaders are allowed
-  const int loader = (gemm_vec(gp, role == R_GAMMA) ? 1 : 0) + (general ? 2 : 0);
+  const int loader = (gemm_vec(gp, role == R_GAMMA || role == R_GAMMA_T, role == R_GAMMA_T) ? 1 : 0) + (general ? 2 : 0);
   const TuneKey key{dev, role, loader, gp.M, gp.N, gp.K, gp.kchunk};
   return tuned(key, nvar, c, st, [&](int v) { return launch_role(role, c[v].bm, gp, st, af, ab, general); });
 }
@@ -592,12 +647,13 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         return rc;
     }
   }
-  for (int64_t k0 = 0; k0 < nocc; k0 += P.g) {
-    const int64_t gc = std::min<int64_t>(P.g, nocc - k0);
-    const double g = (double)gc, slab = 8.0 * g * o * v * v;
+  for (int64_t k0 = 0, gc = 0; k0 < nocc; k0 += gc) {
+    gc = group_at(P, k0);
     // (ia|jb) slab: rows (kk, a) of B starting at k0, columns (j, b) over all of B;
-    // energy only: columns j >= k0 only (pairs j < k come from their mirror)
-    const int64_t j0 = energy_only ? k0 : 0, ncols = nocc - j0, Lc = ncols * nvir;
+    // energy only and the symmetric Gamma path: columns j >= k0 only (pairs
+    // j < k come from their mirror)
+    const int64_t j0 = (energy_only || P.sym) ? k0 : 0, ncols = nocc - j0, Lc = ncols * nvir;
+    const double g = (double)gc, slab = 8.0 * g * (double)ncols * v * v;
     {
       GemmParams gp{};
       gp.M = gc * nvir; gp.N = Lc; gp.K = naux; gp.kchunk = naux;
@@ -611,7 +667,8 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       // algorithmic FLOPs: unordered pairs whose first orbital is in the group
       // (energy only: exactly the pairs (k, j >= k) computed; otherwise the
       // unordered-pair share of the ordered pairs computed)
-      const double npairs = energy_only ? g * o - (g * (double)k0 + g * (g - 1.0) / 2.0) : g * o * (o + 1.0) / (2.0 * o);
+      const double npairs = (energy_only || P.sym) ? g * o - (g * (double)k0 + g * (g - 1.0) / 2.0)
+                                                   : g * o * (o + 1.0) / (2.0 * o);
       const double af = 2.0 * v * v * x * npairs;
       if (P.split) {
         if ((rc = run_oz8(P.sv, dbv, L * P.kpv, k0 * nvir, exv, dbv + j0 * nvir * P.kpv, L * P.kpv, exv + j0 * nvir,
@@ -625,7 +682,7 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
     {
       const int64_t W = amp_splits(gc * ncols, nvir);
       double* epart = (double*)(ws + P.off_epart);
-      const int sym = energy_only ? 1 : (mirror ? 2 : 0);
+      const int sym = energy_only ? 1 : (P.sym ? 3 : (mirror ? 2 : 0));
       if ((rc = check_grid(gc * ncols * W, "amplitude"))) return rc;
       if ((rc = traced(R_AMP, 0, 0, energy_only ? slab : 3.0 * slab, st, [&] {
              hipLaunchKernelGGL(amplitude_kernel, dim3((unsigned)(gc * ncols * W)), dim3(256), 0, st, V, T, eo, ev,
@@ -638,7 +695,50 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
            })))
         return rc;
     }
-    if (P.gamma) {
+    if (P.gamma && P.sym) {
+      // Gamma rows of the group: Gamma[k] (+)= sum over pairs (k, j >= k0) of T_kj B_j
+      const int64_t s_g = sym_gamma_splits(P, k0, gc);
+      const int acc = k0 > 0 ? 1 : 0;   // earlier groups' transposed blocks are already in these rows
+      GemmParams gp{};
+      gp.M = gc * nvir; gp.N = naux; gp.K = Lc;
+      gp.kchunk = cdiv(Lc, s_g);
+      gp.A = kop(T, Lc, INT64_MAX, 0);
+      gp.Bn = NOperand{B + j0 * nvir * naux, naux};
+      gp.status = status;
+      double* out = Gam + k0 * nvir * naux;
+      const double c = (double)ncols;
+      const double af = 2.0 * g * v * x * c * v, ab = slab + 8.0 * c * v * x + 8.0 * (1 + acc) * g * v * x;
+      const int64_t splits = cdiv(Lc, cdiv(cdiv(Lc, s_g), kBK) * kBK);
+      if (splits > 1) {
+        double* W = (double*)(ws + P.off_gam);
+        gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, P.general, st, af, ab))) return rc;
+        const int64_t n = gc * nvir * naux;
+        if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1 + acc) * n, st, [&] {
+               hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, out, naux, W,
+                                  naux, gc * nvir * naux, (int)splits, gc * nvir, naux, 1.0, acc, status);
+             })))
+          return rc;
+      } else {
+        gp.C = out; gp.ldc = naux; gp.split_stride = 0; gp.accumulate = acc;
+        if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, P.general, st, af, ab))) return rc;
+      }
+      // Gamma rows of the later orbitals j >= k0 + gc, from the transposed
+      // blocks: Gamma[j, b, P] += sum over (kk, a) of T_kj[a, b] B[k0 + kk, a, P]
+      // (T_jk = T_kj^T), with the T slab read as an M-contiguous operand
+      if (ncols > gc) {
+        const int64_t rows = (ncols - gc) * nvir;
+        GemmParams gt{};
+        gt.M = rows; gt.N = naux; gt.K = gc * nvir; gt.kchunk = gt.K;
+        gt.Am = NOperand{T + gc * nvir, Lc};
+        gt.Bn = NOperand{B + k0 * nvir * naux, naux};
+        gt.C = Gam + (k0 + gc) * nvir * naux; gt.ldc = naux; gt.split_stride = 0; gt.accumulate = acc;
+        gt.status = status;
+        const double r = (double)(ncols - gc);
+        const double aft = 2.0 * r * v * x * g * v, abt = 8.0 * g * v * r * v + 8.0 * g * v * x + 8.0 * (1 + acc) * r * v * x;
+        if ((rc = launch_tuned(R_GAMMA_T, gt, P.autotune, P.general, st, aft, abt))) return rc;
+      }
+    } else if (P.gamma) {
       GemmParams gp{};
       gp.M = gc * nvir; gp.N = naux; gp.K = L;
       gp.kchunk = cdiv(L, P.s_gam);
