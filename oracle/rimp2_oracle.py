@@ -216,3 +216,29 @@ def gamma_metric(Gamma, Jm):
     fragment kernel's Gamma~ (taken before this contraction; see the module
     header): out[i, a, P] = sum_Q Gamma[i, a, Q] Jm[P, Q]."""
     return Gamma @ Jm.T
+
+
+# ---------------------------------------------------------------------------
+# Adjacent gradient steps (Appendix): the AO back-transform of Gamma and the
+# L' and L'' terms of the energy-weighted density matrix.
+# ---------------------------------------------------------------------------
+
+def gamma_ao(Gamma, C_occ, C_vir):
+    """Gamma^P_ia back-transformed to the AO basis (Appendix, after the
+    definition of Gamma): Gamma^P_mn = sum_ia C_im Gamma^P_ia C_an, with the
+    MO coefficients stored C_occ[i][m] and C_vir[a][n] (the paper's C_imu):
+    out[m, n, P] = sum_i sum_a C_occ[i, m] Gamma[i, a, P] C_vir[a, n]."""
+    return np.einsum("im,iaP,an->mnP", C_occ, Gamma, C_vir)
+
+
+def l_prime(Gamma, I_qa):
+    """L'_iq = sum_aP Gamma^P_ia (P|qa) (Appendix, energy-weighted density),
+    with I_qa[q, a, P] = (P|qa) for every molecular orbital q."""
+    return np.einsum("iaP,qaP->iq", Gamma, I_qa)
+
+
+def l_dprime(Gamma, I_iq):
+    """L''_aq = sum_iP Gamma^P_ia (P|iq) (Appendix, energy-weighted density),
+    with I_iq[i, q, P] = (P|iq) for every molecular orbital q."""
+    return np.einsum("iaP,iqP->aq", Gamma, I_iq)
+

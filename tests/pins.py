@@ -374,3 +374,81 @@ def pin_skip_nothing_is_the_full_result(O):
 
 
 ALL_PINS.extend([pin_skip_all_pairs_of_an_orbital_deletes_it, pin_skip_nothing_is_the_full_result])
+
+
+def pin_gamma_ao_is_ao_derivative(O):
+    """With the MO transform of the paper, B^P_ia = sum_mn C_im C_an B^P_mn
+    (B[i, a, P] = sum_mn C_occ[i, m] C_vir[a, n] B_ao[m, n, P]), the chain
+    rule and dE/dB = 4 Gamma give dE/dB_ao = 4 gamma_ao(Gamma, C_occ, C_vir),
+    checked by complex step of the energy for every element of B_ao.  The
+    coefficient matrices are rectangular and different, so a transposed or
+    swapped one fails."""
+    h = 1e-30
+    nocc, nvir, nao, naux = 2, 3, 4, 3
+    rng = np.random.default_rng(31)
+    C_occ = rng.standard_normal((nocc, nao))
+    C_vir = rng.standard_normal((nvir, nao))
+    B_ao = 0.3 * rng.standard_normal((nao, nao, naux))
+    _, eo, ev = tiny_inputs(nocc, nvir, naux, 32)
+
+    def mo(Bao):
+        return np.einsum("im,an,mnP->iaP", C_occ, C_vir, Bao)
+
+    want = 4.0 * O.gamma_ao(O.fragment(mo(B_ao), eo, ev, density=False)["Gamma"], C_occ, C_vir)
+    got = np.zeros_like(B_ao)
+    for idx in np.ndindex(B_ao.shape):
+        Bc = B_ao.astype(np.complex128)
+        Bc[idx] += 1j * h
+        got[idx] = _complex_E(O, mo(Bc), eo, ev).imag / h
+    assert rel(got, want) <= 1e-12, rel(got, want)
+
+
+def _three_centre_system(seed, nocc=2, nvir=3, naux=4):
+    """Three-centre MO integrals I[Q][p][q] (symmetric in p, q over all
+    nocc + nvir orbitals, occupied first), a non-symmetric metric factor M,
+    and orbital energies."""
+    rng = np.random.default_rng(seed)
+    nmo = nocc + nvir
+    I = 0.3 * rng.standard_normal((naux, nmo, nmo))
+    I = I + I.transpose(0, 2, 1)
+    M = rng.standard_normal((naux, naux))
+    _, eo, ev = tiny_inputs(nocc, nvir, naux, seed + 1)
+    return I, M, eo, ev
+
+
+def pin_l_terms_are_orbital_rotation_derivatives(O):
+    """L'_iq and L'' _aq are a quarter of the derivatives of E with respect
+    to mixing orbital q into occupied orbital i, or into virtual orbital a,
+    in the three-centre integrals (P|ia) from which B = (P|ia) J^{-1/2} is
+    formed: with B3[i, a, Q] = (Q|ia) and B = B3 M,
+      d/dt E(B3[i, :, :] += t (.|q.)) = 4 L'_iq,
+      d/dt E(B3[:, a, :] += t (.|.q)) = 4 L''_aq,
+    where Gamma is gamma_metric(Gamma~, M), the Appendix's Gamma with its
+    metric contraction (complex step, every i, a and q)."""
+    h = 1e-30
+    nocc, nvir, naux = 2, 3, 4
+    I, M, eo, ev = _three_centre_system(41, nocc, nvir, naux)
+    nmo = nocc + nvir
+    B3 = np.transpose(I[:, :nocc, nocc:], (1, 2, 0)).copy()     # B3[i, a, Q] = (Q|ia)
+    I_qa = np.transpose(I[:, :, nocc:], (1, 2, 0)).copy()       # I_qa[q, a, Q] = (Q|qa)
+    I_iq = np.transpose(I[:, :nocc, :], (1, 2, 0)).copy()       # I_iq[i, q, Q] = (Q|iq)
+    G = O.gamma_metric(O.fragment(B3 @ M, eo, ev, density=False)["Gamma"], M)
+    L1 = O.l_prime(G, I_qa)
+    L2 = O.l_dprime(G, I_iq)
+    assert L1.shape == (nocc, nmo) and L2.shape == (nvir, nmo)
+    for i in range(nocc):
+        for q in range(nmo):
+            Bc = B3.astype(np.complex128)
+            Bc[i] += 1j * h * I_qa[q]
+            d = _complex_E(O, Bc @ M, eo, ev).imag / h
+            assert abs(d - 4.0 * L1[i, q]) <= 1e-12 * max(1.0, abs(d)), (i, q, d, 4.0 * L1[i, q])
+    for a in range(nvir):
+        for q in range(nmo):
+            Bc = B3.astype(np.complex128)
+            Bc[:, a, :] += 1j * h * I_iq[:, q, :]
+            d = _complex_E(O, Bc @ M, eo, ev).imag / h
+            assert abs(d - 4.0 * L2[a, q]) <= 1e-12 * max(1.0, abs(d)), (a, q, d, 4.0 * L2[a, q])
+
+
+ALL_PINS.extend([pin_gamma_ao_is_ao_derivative, pin_l_terms_are_orbital_rotation_derivatives])
+

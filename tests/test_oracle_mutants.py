@@ -46,6 +46,14 @@ MUTANTS = [
     ("gamma_metric drops the metric", "return Gamma @ Jm.T", "return Gamma"),
     ("gamma_rows exchange from row", "T = 2.0 * V_row / D - V_col / D", "T = 2.0 * V_row / D - V_row / D"),
     ("gamma_rows wrong exchange index", "V_col = Bj[rows] @ B[i].T", "V_col = B[i][rows] @ Bj.T"),
+    ("gamma_ao coefficients swapped", 'np.einsum("im,iaP,an->mnP", C_occ, Gamma, C_vir)',
+     'np.einsum("an,iaP,im->mnP", C_occ, Gamma, C_vir)'),
+    ("gamma_ao output transposed", 'np.einsum("im,iaP,an->mnP", C_occ, Gamma, C_vir)',
+     'np.einsum("im,iaP,an->nmP", C_occ, Gamma, C_vir)'),
+    ("l_prime aux index not matched", 'np.einsum("iaP,qaP->iq", Gamma, I_qa)', 'np.einsum("iaP,qaQ->iq", Gamma, I_qa)'),
+    ("l_dprime aux index not matched", 'np.einsum("iaP,iqP->aq", Gamma, I_iq)', 'np.einsum("iaP,iqQ->aq", Gamma, I_iq)'),
+    ("l_dprime occupied index not matched", 'np.einsum("iaP,iqP->aq", Gamma, I_iq)',
+     'np.einsum("iaP,jqP->aq", Gamma, I_iq)'),
     ("skip mask read one way only", "(skip[k][j] or skip[j][k])", "skip[k][j]"),
     ("skipped pair still computed", "continue            # screened out", "pass            # screened out"),
     ("pair_energy uses X", "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * V)",

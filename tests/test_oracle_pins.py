@@ -8,6 +8,9 @@ Pin status of every oracle function:
   pair_energy, gamma_row, gamma_rows, p_ab_element, p_ij_element
                               brute force
   exact_sum                   exact cancellation cases
+  gamma_metric                chain rule: dE/dB3 = 4 gamma_metric (complex step)
+  gamma_ao                    chain rule through the MO transform (complex step)
+  l_prime, l_dprime           orbital-mixing derivatives of E (complex step)
 No function is unpinned.
 """
 import pytest
