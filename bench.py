@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--screen-train", type=int, default=200, help="screen: training systems (seeds 4000..)")
     ap.add_argument("--screen-pairs", type=int, default=128, help="screen: sampled pairs per training system")
     ap.add_argument("--screen-size", type=str, default="400,2400,7200", help="screen: nocc,nvir,naux")
+    ap.add_argument("--screen-save", type=str, default="",
+                    help="screen: write the trained network (parameters and metadata, .npz) to this path")
     ap.add_argument("--mbe3-stride", type=int, default=32,
                     help="mbe3: take every n-th of the 4096 recipe fragments")
     ap.add_argument("--mbe3-kinds", type=str, default="1,2,3",
@@ -744,24 +746,34 @@ def bench_screen(args, torch, synth, rm, dev):
 
     # literal threshold (1e-7 Eh) and the budgeted threshold
     lit, lit_e = SC.screen_mask(pred, nocc, -7.0)
-    lo, hi = -20.0, 0.0
-    for _ in range(50):
-        mid = 0.5 * (lo + hi)
-        _, se = SC.screen_mask(pred, nocc, mid)
-        lo, hi = (mid, hi) if float(se) <= 0.5e-6 else (lo, mid)
-    bud, bud_e = SC.screen_mask(pred, nocc, lo)
-    t1 = run(eo, ev, bud)
-    E1 = E.cpu().numpy().copy()
-    dE_run = abs(math.fsum([float(E1[0]), float(E1[1]), -float(E0[0]), -float(E0[1])]))
-    print("[bench] screened run %.3f s" % t1, file=sys.stderr, flush=True)
+    lo = SC.budget_threshold(pred, nocc, 0.5e-6)
+    # the unscreened run judges each screened run; over the 1 uEh budget the
+    # threshold is lowered by half a decade and the screened run repeated, and
+    # after three failures the unscreened result stands (the fallback)
+    attempts, t_screened, fallback = [], 0.0, False
+    while True:
+        bud, bud_e = SC.screen_mask(pred, nocc, lo)
+        t1 = run(eo, ev, bud)
+        t_screened += t1
+        E1 = E.cpu().numpy().copy()
+        dE_run = abs(math.fsum([float(E1[0]), float(E1[1]), -float(E0[0]), -float(E0[1])]))
+        attempts.append({"threshold_log10": lo, "s": round(t1, 3), "abs_dE_Eh": dE_run})
+        print("[bench] screened run %.3f s, |dE| %.3g Eh" % (t1, dE_run), file=sys.stderr, flush=True)
+        if dE_run <= 1e-6:
+            break
+        if len(attempts) == 3:
+            fallback = True
+            t1, E1, dE_run = t0, E0, 0.0
+            break
+        lo -= 0.5
     # rigorous bound screen with the same budget: skip the smallest bounds while their sum <= 1 uEh
-    bd = bound.cpu().numpy()
-    order = np.argsort(bd[iu])
-    csum = np.cumsum(2 * bd[iu][order])
-    nb = int(np.searchsorted(csum, 1e-6, side="right"))
-    bmask = np.zeros((nocc, nocc), dtype=np.uint8)
-    bmask[iu[0][order[:nb]], iu[1][order[:nb]]] = 1
-    bmask |= bmask.T
+    bmask = SC.bound_mask(bound, 1e-6).cpu().numpy()
+    nb = int(bmask[iu].sum())
+    if args.screen_save:
+        SC.save_params(args.screen_save, tr.params, train_seeds=[4000, 4000 + args.screen_train - 1],
+                       pairs_per_system=args.screen_pairs, size=[nocc, nvir, naux], eval_seed=4200,
+                       rmse_log10_eval=rmse, features="|r_i-r_j|/10, log||B_i||, log||B_j||, (eps_i+eps_j)/10",
+                       target="log10|e_ij|")
     npairs = nocc * (nocc - 1)
     lit_np, bud_np = lit.cpu().numpy(), bud.cpu().numpy()
     alg = float(nocc) * (nocc + 1) * nvir * nvir * naux
@@ -775,13 +787,16 @@ def bench_screen(args, torch, synth, rm, dev):
                    "train_pairs": int(len(T)), "eval_seed": 4200,
                    "flops_counted": "algorithmic full energy nocc(nocc+1) nvir^2 naux"},
         "unscreened_s": round(t0, 3), "screened_s": round(t1, 3), "speedup_screened_vs_unscreened": round(t0 / t1, 4),
+        "judge": {"budget_Eh": 1e-6, "passed": not fallback, "fallback_to_unscreened": fallback,
+                  "attempts": attempts, "screened_time_incl_failed_attempts_s": round(t_screened, 3)},
         "screen_budgeted": {"threshold_log10": lo, "skipped_pair_fraction": float(bud_np[off].mean()),
                             "predicted_skipped_Eh": float(bud_e), "exact_skipped_Eh": exact_error(bud_np),
                             "abs_dE_run_Eh": dE_run},
         "screen_literal_1e-7": {"skipped_pair_fraction": float(lit_np[off].mean()),
                                 "predicted_skipped_Eh": float(lit_e), "exact_skipped_Eh": exact_error(lit_np)},
         "bound_screen_1uEh": {"skipped_pair_fraction": nb * 2 / npairs, "exact_skipped_Eh": exact_error(bmask)},
-        "model": {"rmse_log10_eval": rmse, "train_data_s": round(t_data, 1), "train_fit_s": round(t_fit, 1)},
+        "model": {"rmse_log10_eval": rmse, "train_data_s": round(t_data, 1), "train_fit_s": round(t_fit, 1),
+                  "saved_to": args.screen_save or None},
         "E_unscreened": [float(E0[0]), float(E0[1])],
         "roofline": {"bound": "mfma", "kernel": "ints_gemm", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None},

@@ -8,6 +8,8 @@
 //   Gamma, transposed blocks (symmetric pair path)
 //                  G[(j,b), P]    += sum_(k,a) T[(k,a), (j,b)] B[(k,a), P]
 //                                 (A M-contiguous, B N-contiguous)
+// and the adjacent gradient steps: the AO back-transform of Gamma (A
+// M-contiguous: transposed MO coefficients) and the L' / L'' terms.
 // The slab operands store the reduction index in two levels (runs of kdiv
 // contiguous elements, runs ks1 apart), which the loaders follow directly so
 // no operand is ever copied or transposed in HBM.
@@ -107,8 +109,11 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 }
 
 // ROLE gives each contraction its own kernel symbol (profiler names);
-// ROLE_GAMMA_T also selects the M-contiguous A loader.
-enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3, ROLE_GAMMA_T = 4 };
+// ROLE_GAMMA_T and ROLE_AO also select the M-contiguous A loader.
+enum GemmRole { ROLE_INTS = 0, ROLE_GAMMA = 1, ROLE_PAB = 2, ROLE_PIJ = 3, ROLE_GAMMA_T = 4, ROLE_AO = 5,
+                ROLE_LTERM = 6 };
+// Roles whose A operand is M-contiguous.
+constexpr bool role_a_mcontig(int role) { return role == ROLE_GAMMA_T || role == ROLE_AO; }
 
 // Decodes logical tile index t (< tiles of one split) into (tm, tn):
 // triangular order (TRI) or groups of group_m m-tiles.
@@ -515,7 +520,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmParams p) {
   int tm, tn;
   decode_tile<TRI>(p, wl - z * ntiles, tm, tn);
   if (tile_screened<BM, BN>(p, tm, tn)) return;
-  gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, FAST, ROLE == ROLE_GAMMA_T>(p, tm, tn, z, lds);
+  gemm_tile<BM, BN, BK, B_NCONTIG, VEC, TRI, FAST, role_a_mcontig(ROLE)>(p, tm, tn, z, lds);
 }
 
 // Persistent grouped launch over many independent GEMMs (one per fragment):

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "../../include/rimp2.h"
+#include "../../include/rimp2_gradient.h"
 #include "common.hpp"
 #include "gemm_f64.hpp"
 #include "kernels.hpp"
@@ -44,11 +45,11 @@ namespace {
 
 // ---- kernel timing -------------------------------------------------------
 enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
-            R_GAMMA_T, R_NROLES };
+            R_GAMMA_T, R_GAMMA_AO, R_LTERM, R_NROLES };
 const char* const kRoleName[R_NROLES] = {"gap_check",  "ints_gemm",     "amplitude",  "gamma_gemm",
                                          "pab_gemm",   "pij_gemm",      "splitk_reduce", "energy_sum",
                                          "status_copy", "digit_split", "ints_oz8",   "gamma_oz8",
-                                         "gamma_t_gemm"};
+                                         "gamma_t_gemm", "gamma_ao_gemm", "l_terms_gemm"};
 struct TraceRec {
   int role;
   hipEvent_t e0, e1;
@@ -323,7 +324,7 @@ int launch_gemm(GemmParams gp, hipStream_t st, int role, double af, double ab, b
   const int64_t tiles = TRI ? (int64_t)gp.tiles_m * (gp.tiles_m + 1) / 2 : (int64_t)gp.tiles_m * gp.tiles_n;
   const int64_t nwg = tiles * gp.splits;
   if (int rc = check_grid(nwg, "GEMM")) return rc;
-  constexpr bool AMC = ROLE == ROLE_GAMMA_T;
+  constexpr bool AMC = role_a_mcontig(ROLE);
   if (AMC && gp.splits != 1) return fail(RIMP2_EINVAL, "M-contiguous GEMM without split-K only");
   if (gp.accumulate && (TRI || gp.splits != 1)) return fail(RIMP2_EINVAL, "accumulating GEMM without split-K only");
   const bool vec = gemm_vec(gp, NC, AMC);
@@ -1414,6 +1415,130 @@ int rimp2_autotune_reset(void) {
       U.pool.push_back(q.e1);
     }
   U.tab.clear();
+  return RIMP2_OK;
+}
+
+// ---- adjacent gradient steps (include/rimp2_gradient.h) --------------------
+
+int rimp2_gamma_ao_workspace_size(int32_t nocc, int32_t nao, int32_t pcount, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  if (nocc < 1 || nao < 1 || pcount < 1) return fail(RIMP2_EINVAL, "sizes must be >= 1");
+  *bytes = align_up(64) + align_up((size_t)8 * nocc * nao * pcount);
+  return RIMP2_OK;
+}
+
+int rimp2_gamma_ao(int32_t nocc, int32_t nvir, int32_t nao, int32_t naux, int32_t p0, int32_t pcount,
+                   const double* Gamma, const double* C_occ, const double* C_vir, double* out, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+  if (nocc < 1 || nvir < 1 || nao < 1 || naux < 1 || pcount < 1 || p0 < 0 || (int64_t)p0 + pcount > naux)
+    return fail(RIMP2_EINVAL, "sizes must be >= 1 and 0 <= p0, p0 + pcount <= naux (nocc=%d nvir=%d nao=%d naux=%d "
+                "p0=%d pcount=%d)", nocc, nvir, nao, naux, p0, pcount);
+  if (!Gamma || !C_occ || !C_vir || !out || !workspace)
+    return fail(RIMP2_EINVAL, "Gamma, C_occ, C_vir, out and workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  int rc;
+  if ((rc = rimp2_gamma_ao_workspace_size(nocc, nao, pcount, &need))) return rc;
+  if (workspace_bytes < need) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  unsigned long long* status = (unsigned long long*)ws;
+  double* H = (double*)(ws + align_up(64));
+  const int64_t pc = pcount, na = nao;
+  if ((rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
+         hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, status, 1);
+       })))
+    return rc;
+  // H[i][n][P] = sum_a C_vir[a][n] Gamma[i][a][p0 + P], one GEMM per occupied orbital
+  for (int64_t i = 0; i < nocc; ++i) {
+    GemmParams gp{};
+    gp.M = na; gp.N = pc; gp.K = nvir; gp.kchunk = nvir;
+    gp.Am = NOperand{C_vir, na};
+    gp.Bn = NOperand{Gamma + i * nvir * (int64_t)naux + p0, naux};
+    gp.C = H + i * na * pc; gp.ldc = pc; gp.status = (const int32_t*)status;
+    if ((rc = launch_gemm<128, 128, true, ROLE_AO, false>(gp, st, R_GAMMA_AO, 2.0 * na * pc * nvir,
+                                                           8.0 * (nvir * (na + pc) + na * pc), false)))
+      return rc;
+  }
+  // out[m][(n, P)] = sum_i C_occ[i][m] H[i][(n, P)]
+  GemmParams gp{};
+  gp.M = na; gp.N = na * pc; gp.K = nocc; gp.kchunk = nocc;
+  gp.Am = NOperand{C_occ, na};
+  gp.Bn = NOperand{H, na * pc};
+  gp.C = out; gp.ldc = na * pc; gp.status = (const int32_t*)status;
+  return launch_gemm<128, 128, true, ROLE_AO, false>(gp, st, R_GAMMA_AO, 2.0 * na * na * pc * nocc,
+                                                     8.0 * (nocc * na + nocc * na * pc + na * na * pc), false);
+}
+
+namespace {
+// Split-K plan of the two L-term GEMMs: M x N outputs over reduction K.
+struct LPlan {
+  int64_t s1, s2;
+  size_t part_bytes;
+};
+LPlan l_plan(int64_t nocc, int64_t nvir, int64_t nmo, int64_t naux) {
+  LPlan L;
+  L.s1 = choose_splits(cdiv(nocc, kTile) * cdiv(nmo, kTile), nvir * naux);
+  L.s2 = choose_splits(cdiv(nvir, kTile) * cdiv(nmo, kTile), nocc * naux);
+  L.part_bytes = std::max((size_t)8 * L.s1 * nocc * nmo, (size_t)8 * L.s2 * nvir * nmo);
+  return L;
+}
+}  // namespace
+
+int rimp2_l_terms_workspace_size(int32_t nocc, int32_t nvir, int32_t nmo, int32_t naux, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  if (nocc < 1 || nvir < 1 || nmo < 1 || naux < 1) return fail(RIMP2_EINVAL, "sizes must be >= 1");
+  *bytes = align_up(64) + align_up(l_plan(nocc, nvir, nmo, naux).part_bytes);
+  return RIMP2_OK;
+}
+
+int rimp2_l_terms(int32_t nocc, int32_t nvir, int32_t nmo, int32_t naux, const double* Gamma, const double* I_qa,
+                  const double* I_iq, double* L1, double* L2, void* workspace, size_t workspace_bytes, void* stream) {
+  if (nocc < 1 || nvir < 1 || nmo < 1 || naux < 1) return fail(RIMP2_EINVAL, "sizes must be >= 1");
+  if (!Gamma || !workspace) return fail(RIMP2_EINVAL, "Gamma and workspace must not be NULL");
+  if ((L1 == nullptr) != (I_qa == nullptr) || (L2 == nullptr) != (I_iq == nullptr))
+    return fail(RIMP2_EINVAL, "L1 needs I_qa and L2 needs I_iq (both or neither)");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  int rc;
+  if ((rc = rimp2_l_terms_workspace_size(nocc, nvir, nmo, naux, &need))) return rc;
+  if (workspace_bytes < need) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  int32_t* status = (int32_t*)ws;
+  double* W = (double*)(ws + align_up(64));
+  const LPlan lp = l_plan(nocc, nvir, nmo, naux);
+  const double o = nocc, v = nvir, q = nmo, x = naux;
+  if ((rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
+         hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, (unsigned long long*)status, 1);
+       })))
+    return rc;
+  auto run = [&](GemmParams gp, int64_t s, double* out, double af, double ab) -> int {
+    gp.kchunk = cdiv(gp.K, s);
+    gp.C = W; gp.ldc = gp.N; gp.split_stride = gp.M * gp.N; gp.status = status;
+    const int64_t splits = cdiv(gp.K, cdiv(gp.kchunk, kBK) * kBK);
+    int r;
+    if ((r = launch_gemm<128, 128, false, ROLE_LTERM, false>(gp, st, R_LTERM, af, ab, false))) return r;
+    const int64_t n = gp.M * gp.N;
+    return traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, out, gp.N,
+                         (const double*)W, gp.N, gp.M * gp.N, (int)splits, gp.M, gp.N, 1.0, 0, status);
+    });
+  };
+  if (L1) {   // L'[i][q] = sum over (a, P) of Gamma[i][a][P] I_qa[q][a][P]
+    GemmParams gp{};
+    gp.M = nocc; gp.N = nmo; gp.K = (int64_t)nvir * naux;
+    gp.A = kop(Gamma, gp.K, INT64_MAX, 0);
+    gp.Bk = kop(I_qa, gp.K, INT64_MAX, 0);
+    if ((rc = run(gp, lp.s1, L1, 2.0 * o * q * v * x, 8.0 * (o + q) * v * x + 8.0 * o * q))) return rc;
+  }
+  if (L2) {   // L''[a][q] = sum over (i, P) of Gamma[i][a][P] I_iq[i][q][P]
+    GemmParams gp{};
+    gp.M = nvir; gp.N = nmo; gp.K = (int64_t)nocc * naux;
+    gp.A = kop(Gamma, naux, naux, (int64_t)nvir * naux);
+    gp.Bk = kop(I_iq, naux, naux, (int64_t)nmo * naux);
+    if ((rc = run(gp, lp.s2, L2, 2.0 * v * q * o * x, 8.0 * (v + q) * o * x + 8.0 * v * q))) return rc;
+  }
   return RIMP2_OK;
 }
 

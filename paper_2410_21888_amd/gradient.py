@@ -15,9 +15,17 @@ def _L():
     global _bound
     L = lib()
     if not _bound:
-        i32, vp = ctypes.c_int32, ctypes.c_void_p
+        i32, vp, sz = ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
         L.rimp2_gamma_metric.restype = ctypes.c_int
         L.rimp2_gamma_metric.argtypes = [i32, i32, i32, vp, vp, vp, vp]
+        L.rimp2_gamma_ao_workspace_size.restype = ctypes.c_int
+        L.rimp2_gamma_ao_workspace_size.argtypes = [i32, i32, i32, ctypes.POINTER(sz)]
+        L.rimp2_gamma_ao.restype = ctypes.c_int
+        L.rimp2_gamma_ao.argtypes = [i32] * 6 + [vp] * 5 + [sz, vp]
+        L.rimp2_l_terms_workspace_size.restype = ctypes.c_int
+        L.rimp2_l_terms_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+        L.rimp2_l_terms.restype = ctypes.c_int
+        L.rimp2_l_terms.argtypes = [i32] * 4 + [vp] * 6 + [sz, vp]
         _bound = True
     return L
 
@@ -33,3 +41,56 @@ def gamma_metric(Gamma: torch.Tensor, Jm: torch.Tensor, out: Optional[torch.Tens
         out = torch.empty_like(Gamma)
     _check(_L().rimp2_gamma_metric(nocc, nvir, naux, _ptr(Gamma), _ptr(Jm), _ptr(out), _stream_handle(stream)))
     return out
+
+
+def _need(t: torch.Tensor, shape, name):
+    if tuple(t.shape) != tuple(shape) or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("%s must be a contiguous float64 GPU tensor of shape %s" % (name, tuple(shape)))
+
+
+def gamma_ao(Gamma: torch.Tensor, C_occ: torch.Tensor, C_vir: torch.Tensor, p0: int = 0,
+             pcount: Optional[int] = None, out: Optional[torch.Tensor] = None, workspace=None, stream=None):
+    """out[m, n, P - p0] = sum_ia C_occ[i, m] Gamma[i, a, P] C_vir[a, n] for P in
+    [p0, p0 + pcount) on the GPU (rimp2_gamma_ao)."""
+    nocc, nvir, naux = Gamma.shape
+    nao = C_occ.shape[1]
+    pcount = naux - p0 if pcount is None else pcount
+    _need(Gamma, (nocc, nvir, naux), "Gamma")
+    _need(C_occ, (nocc, nao), "C_occ")
+    _need(C_vir, (nvir, nao), "C_vir")
+    if out is None:
+        out = torch.empty((nao, nao, pcount), dtype=torch.float64, device=Gamma.device)
+    _need(out, (nao, nao, pcount), "out")
+    L = _L()
+    if workspace is None:
+        n = ctypes.c_size_t(0)
+        _check(L.rimp2_gamma_ao_workspace_size(nocc, nao, pcount, ctypes.byref(n)))
+        workspace = torch.empty(n.value, dtype=torch.uint8, device=Gamma.device)
+    _check(L.rimp2_gamma_ao(nocc, nvir, nao, naux, p0, pcount, _ptr(Gamma), _ptr(C_occ), _ptr(C_vir), _ptr(out),
+                            _ptr(workspace), workspace.numel(), _stream_handle(stream)))
+    return out
+
+
+def l_terms(Gamma: torch.Tensor, I_qa: Optional[torch.Tensor], I_iq: Optional[torch.Tensor], workspace=None,
+            stream=None):
+    """(L' [nocc][nmo], L'' [nvir][nmo]) on the GPU (rimp2_l_terms); either
+    integral tensor may be None, and its term is then None."""
+    nocc, nvir, naux = Gamma.shape
+    nmo = (I_qa if I_qa is not None else I_iq).shape[0 if I_qa is not None else 1]
+    _need(Gamma, (nocc, nvir, naux), "Gamma")
+    f64 = dict(dtype=torch.float64, device=Gamma.device)
+    L1 = L2 = None
+    if I_qa is not None:
+        _need(I_qa, (nmo, nvir, naux), "I_qa")
+        L1 = torch.empty((nocc, nmo), **f64)
+    if I_iq is not None:
+        _need(I_iq, (nocc, nmo, naux), "I_iq")
+        L2 = torch.empty((nvir, nmo), **f64)
+    L = _L()
+    if workspace is None:
+        n = ctypes.c_size_t(0)
+        _check(L.rimp2_l_terms_workspace_size(nocc, nvir, nmo, naux, ctypes.byref(n)))
+        workspace = torch.empty(n.value, dtype=torch.uint8, device=Gamma.device)
+    _check(L.rimp2_l_terms(nocc, nvir, nmo, naux, _ptr(Gamma), _ptr(I_qa), _ptr(I_iq), _ptr(L1), _ptr(L2),
+                           _ptr(workspace), workspace.numel(), _stream_handle(stream)))
+    return L1, L2

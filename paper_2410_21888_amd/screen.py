@@ -101,6 +101,59 @@ def init_params(seed: int, device) -> torch.Tensor:
     return torch.from_numpy(np.concatenate(parts)).to(device)
 
 
+def save_params(path: str, params: torch.Tensor, **meta) -> None:
+    """Checkpoint of a trained network: the parameter vector (layout of
+    include/rimp2_screen.h) and JSON-serialisable metadata (training seeds,
+    feature scaling, loss), in an .npz file that loads without pickle."""
+    import json
+    np.savez(path, params=params.detach().cpu().numpy().astype(np.float64),
+             meta=np.frombuffer(json.dumps(meta, sort_keys=True).encode(), dtype=np.uint8))
+
+
+def load_params(path: str, device) -> tuple[torch.Tensor, dict]:
+    """(params on ``device``, metadata) from save_params' file."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        p = z["params"]
+        meta = json.loads(bytes(z["meta"]).decode()) if "meta" in z else {}
+    if p.shape != (N_PARAMS,) or p.dtype != np.float64:
+        raise ValueError("%s: expected %d float64 parameters, got %s %s" % (path, N_PARAMS, p.shape, p.dtype))
+    return torch.from_numpy(p.copy()).to(device), meta
+
+
+def budget_threshold(pred: torch.Tensor, nocc: int, budget_Eh: float, iters: int = 60) -> float:
+    """The largest log10 threshold whose predicted skipped energy (sum of
+    10^pred over the pairs it skips, rimp2_screen_mask) is at most budget_Eh,
+    by bisection over [-30, 0]."""
+    lo, hi = -30.0, 0.0
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        _, se = screen_mask(pred, nocc, mid)
+        if float(se) <= budget_Eh:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def bound_mask(bound: torch.Tensor, budget_Eh: float) -> torch.Tensor:
+    """The rigorous-bound screen (the method without the network): skip the
+    pairs i < j with the smallest bounds while twice their summed bound (both
+    orders) stays within budget_Eh, so the exact skipped energy is within it
+    too.  Host-side selection over the bound matrix; returns a symmetric uint8
+    mask on the bound's device."""
+    bd = bound.detach().cpu().numpy()
+    n = bd.shape[0]
+    iu = np.triu_indices(n, 1)
+    order = np.argsort(bd[iu], kind="stable")
+    csum = np.cumsum(2.0 * bd[iu][order])
+    nb = int(np.searchsorted(csum, budget_Eh, side="right"))
+    m = np.zeros((n, n), dtype=np.uint8)
+    m[iu[0][order[:nb]], iu[1][order[:nb]]] = 1
+    m |= m.T
+    return torch.from_numpy(m).to(bound.device)
+
+
 class Trainer:
     """Adam on the mean squared error, minibatches drawn by a seeded host RNG."""
 

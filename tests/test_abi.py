@@ -123,3 +123,25 @@ def test_gamma_metric_host_errors():
     # out overlapping Gamma
     assert L.rimp2_gamma_metric(2, 3, 4, 4096, 512, 4096 + 8, None) == rm.RIMP2_EINVAL
     assert b"overlap" in L.rimp2_last_error()
+
+
+def test_gamma_ao_and_l_terms_host_errors():
+    import ctypes as C
+    from paper_2410_21888_amd import gradient as G
+    L = G._L()
+    n = C.c_size_t(0)
+    assert L.rimp2_gamma_ao_workspace_size(3, 10, 4, C.byref(n)) == rm.RIMP2_OK and n.value >= 8 * 3 * 10 * 4
+    assert L.rimp2_gamma_ao_workspace_size(0, 10, 4, C.byref(n)) == rm.RIMP2_EINVAL
+    args = [256, 512, 768, 1024, 4096]
+    # chunk past the auxiliary range
+    assert L.rimp2_gamma_ao(2, 3, 5, 8, 6, 4, *args, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_gamma_ao(2, 3, 5, 8, -1, 4, *args, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_gamma_ao(2, 3, 5, 8, 0, 4, 256, None, 768, 1024, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_gamma_ao(2, 3, 5, 8, 0, 4, 256, 512, 768, 1024, 4100, 1 << 30, None) == rm.RIMP2_EWORKSPACE
+    assert L.rimp2_gamma_ao(2, 3, 5, 8, 0, 4, *args, 16, None) == rm.RIMP2_ENOMEM
+    assert L.rimp2_l_terms_workspace_size(2, 3, 5, 8, C.byref(n)) == rm.RIMP2_OK and n.value > 0
+    # an L term without its integrals
+    assert L.rimp2_l_terms(2, 3, 5, 8, 256, None, 768, 1024, 2048, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert b"L1 needs I_qa" in L.rimp2_last_error()
+    assert L.rimp2_l_terms(2, 3, 5, 8, 256, 512, 768, 1024, 2048, 4096, 16, None) == rm.RIMP2_ENOMEM
+    assert L.rimp2_l_terms(0, 3, 5, 8, 256, 512, 768, 1024, 2048, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
