@@ -132,6 +132,8 @@ def make_opts(precision: int = FP64, split_slices: int = 0, slab_group: int = 0,
     o.split_slices_gamma = split_slices_gamma
     o.slab_budget_bytes = slab_budget_bytes
     o.pair_skip = pair_skip.data_ptr() if pair_skip is not None else None
+    # the struct holds a raw device address: keep the mask tensor alive with it
+    o._pair_skip_ref = pair_skip
     return o
 
 

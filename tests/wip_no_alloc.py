@@ -1,0 +1,112 @@
+"""rimp2_fragment_noalloc (the entry point that allocates nothing) against
+rimp2_fragment, through the C ABI.
+
+Two calls in a row share the GPU's fixed scratch array, the second with a
+smaller fragment, so whatever the first left there must not leak into the
+second.  With the same slab group both entry points run the same kernels in
+the same order: outputs are compared bit for bit, and with the library's own
+slab choice (which for the scratch array can differ) element by element
+within |d| <= 1e-12 |ref| + 1e-12 max|ref row| and against the oracle.  A
+fragment whose workspace cannot fit the array is refused with RIMP2_ENOMEM
+before anything is enqueued, and the device status (an orbital-energy gap)
+comes back through status_dev.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rimp2_oracle as O
+import paper_2410_21888_amd as rm
+from paper_2410_21888_amd import rimp2 as R
+from gpu_util import to_dev, energy_error, say, assert_elementwise
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _fn():
+    L = R.lib()
+    f = L.rimp2_fragment_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_void_p] * 9 + [ctypes.POINTER(R.Opts), ctypes.c_void_p]
+    return f
+
+
+def noalloc(B, eo, ev, opts=None, gamma=True, density=True):
+    nocc, nvir, naux = B.shape
+    f64 = dict(dtype=torch.float64, device=B.device)
+    E = torch.full((2,), float("nan"), **f64)
+    G = torch.full((nocc, nvir, naux), float("nan"), **f64) if gamma else None
+    Pij = torch.full((nocc, nocc), float("nan"), **f64) if density else None
+    Pab = torch.full((nvir, nvir), float("nan"), **f64) if density else None
+    ep = torch.full((nocc, nocc), float("nan"), **f64)
+    status = torch.full((1,), 7, dtype=torch.int32, device=B.device)
+    p = lambda t: None if t is None else t.data_ptr()
+    rc = _fn()(nocc, nvir, naux, p(B), p(eo), p(ev), p(E), p(G), p(Pij), p(Pab), p(ep), p(status),
+               ctypes.byref(opts) if opts is not None else None, torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise R.Rimp2Error(rc, R.lib().rimp2_last_error().decode())
+    torch.cuda.synchronize()
+    return rm.Result(E, G, Pij, Pab, ep), int(status.item())
+
+
+def test_noalloc_matches_fragment_on_two_calls():
+    cases = [(12, 150, 200, 3, 11), (5, 70, 90, 2, 12)]   # the second call is smaller
+    for nocc, nvir, naux, g, seed in cases:
+        f = synth.random_fragment(nocc, nvir, naux, seed=seed)
+        B, eo, ev = f.arrays()
+        dB, deo, dev_ = to_dev(B, eo, ev)
+        say("noalloc call nocc=%d nvir=%d naux=%d slab_group=%d" % (nocc, nvir, naux, g))
+        opts = R.make_opts(slab_group=g)
+        got, st = noalloc(dB, deo, dev_, opts)
+        assert st == rm.RIMP2_OK
+        ref = rm.fragment(dB, deo, dev_, opts=opts)
+        for name, a, b in zip(ref._fields, got, ref):
+            assert torch.equal(a, b), name
+        # the library's own slab choice, against rimp2_fragment and the oracle
+        got2, st = noalloc(dB, deo, dev_)
+        assert st == rm.RIMP2_OK
+        ref2 = rm.fragment(dB, deo, dev_)
+        orc = O.fragment(B, eo, ev)
+        assert energy_error(got2.E, orc["E_hi"], orc["E_lo"]) <= 1e-12 * abs(orc["E_hi"])
+        for key in ("Gamma", "P_ij", "P_ab", "e_pair"):
+            g2 = getattr(got2, key).cpu().numpy()
+            assert_elementwise(g2, getattr(ref2, key).cpu().numpy(), 1e-12, 1e-12, key)
+            assert_elementwise(g2, orc[key], 1e-12, 1e-12, key)
+
+
+def test_noalloc_symmetric_gamma_and_energy_only():
+    f = synth.random_fragment(9, 64, 100, seed=13)
+    B, eo, ev = f.arrays()
+    d = to_dev(B, eo, ev)
+    for gamma in (True, False):
+        got, st = noalloc(*d, gamma=gamma, density=False)
+        ref = rm.fragment(*d, gamma=gamma, density=False)
+        assert st == rm.RIMP2_OK
+        assert energy_error(got.E, ref.E_hi, ref.E_lo) <= 1e-12 * abs(ref.E_hi)
+        assert_elementwise(got.e_pair.cpu().numpy(), ref.e_pair.cpu().numpy(), 1e-12, 1e-15, "e_pair")
+        if gamma:
+            assert_elementwise(got.Gamma.cpu().numpy(), ref.Gamma.cpu().numpy(), 1e-12, 1e-12, "Gamma")
+
+
+def test_noalloc_limits_and_status():
+    L = R.lib()
+    fn = _fn()
+    # too large for the scratch array even with one orbital per group: refused on the host
+    big = (64, 4000, 200)
+    rc = fn(*big, 256, 512, 768, 1024, None, None, None, None, None, None, None)
+    assert rc == rm.RIMP2_ENOMEM
+    assert b"scratch" in L.rimp2_last_error()
+    rc = fn(4, 5, 6, 256, 512, 768, 1024, None, None, None, None, None, ctypes.byref(R.make_opts(autotune=True)),
+            None)
+    assert rc == rm.RIMP2_ENOTSUP
+    # an orbital-energy gap reaches status_dev
+    f = synth.random_fragment(3, 8, 10, seed=10)
+    B, eo, ev = f.arrays()
+    ev = ev.copy()
+    ev[0] = eo.max() - 1e-3
+    _, st = noalloc(*to_dev(B, eo, ev))
+    assert st == rm.RIMP2_EGAP
