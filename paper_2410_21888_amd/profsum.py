@@ -35,7 +35,8 @@ CSRC = os.path.join(HERE, "csrc")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 CALIB_BYTES = 1 << 30        # bench.py --calib-copy moves 1 GiB each way
 
-_GEMM_ROLES = {"0": "ints_gemm", "1": "gamma_gemm", "2": "pab_gemm", "3": "pij_gemm"}
+_GEMM_ROLES = {"0": "ints_gemm", "1": "gamma_gemm", "2": "pab_gemm", "3": "pij_gemm", "4": "gamma_t_gemm",
+               "5": "gamma_ao_gemm", "6": "l_terms_gemm"}
 
 
 # the sources the fragment path's kernels are built from (screening and the
