@@ -242,3 +242,73 @@ def l_dprime(Gamma, I_iq):
     with I_iq[i, q, P] = (P|iq) for every molecular orbital q."""
     return np.einsum("iaP,iqP->aq", Gamma, I_iq)
 
+
+# ---------------------------------------------------------------------------
+# Orbital-response steps (Appendix): the antisymmetrised-integral term, the
+# Z-vector equation for the occupied-virtual block of the MP2 density, and the
+# energy-weighted density matrix.  Bf[p, q, P] is the three-index factor over
+# every pair of molecular orbitals (occupied first, symmetric in p and q); its
+# occupied-virtual block Bf[i, nocc + a] is the fragment kernel's B[i, a].
+# ---------------------------------------------------------------------------
+
+def antisym_term(Bf, D):
+    """F[p, q] = sum_rs G_pq^rs D_rs, with the Appendix's antisymmetrised
+    integrals G_pq^rs = 2 (pq|rs) - (ps|rq) and (pq|rs) = sum_P Bf[p, q, P]
+    Bf[r, s, P] (RI)."""
+    coulomb = np.einsum("pqP,rsP,rs->pq", Bf, Bf, D)
+    exchange = np.einsum("psP,rqP,rs->pq", Bf, Bf, D)
+    return 2.0 * coulomb - exchange
+
+
+def zvector(Bf, eps_occ, eps_vir, D_oo, D_vv, L1, L2):
+    """The occupied-virtual block D_ai of the MP2 density from the Appendix's
+    Z-vector equation,
+
+      L''_ai - L'_ia - sum_pq G_ai^pq Dbar_pq
+          = (eps_a - eps_i)/2 D_ai + sum_bj G_ai^bj D_bj,
+
+    with Dbar = D_ij (+) D_ab (zero occupied-virtual blocks), L1 = L' [nocc][nmo]
+    and L2 = L'' [nvir][nmo] (column q an MO index).  The left side is the
+    right-hand vector; the right side's operator is assembled as the matrix
+    A[(a,i), (b,j)] = delta_ab delta_ij (eps_a - eps_i)/2 + 2 (ai|bj) - (aj|bi)
+    and the system is solved directly.  Returns D_ai as [nvir][nocc]."""
+    nocc, nvir = len(eps_occ), len(eps_vir)
+    nmo = nocc + nvir
+    Dbar = np.zeros((nmo, nmo), dtype=np.result_type(Bf, D_oo, D_vv))
+    Dbar[:nocc, :nocc] = D_oo
+    Dbar[nocc:, nocc:] = D_vv
+    rhs = L2[:, :nocc] - L1[:, nocc:].T - antisym_term(Bf, Dbar)[nocc:, :nocc]
+    Bvo = Bf[nocc:, :nocc]                                    # [a][i][P]
+    coulomb = np.einsum("aiP,bjP->aibj", Bvo, Bvo)            # (ai|bj)
+    exchange = np.einsum("ajP,biP->aibj", Bvo, Bvo)           # (aj|bi)
+    A = 2.0 * coulomb - exchange
+    nov = nvir * nocc
+    A = A.reshape(nov, nov) + np.diag(((eps_vir[:, None] - eps_occ[None, :]) / 2.0).ravel())
+    return np.linalg.solve(A, rhs.ravel()).reshape(nvir, nocc)
+
+
+def energy_weighted_density(Bf, eps_occ, eps_vir, D_oo, D_vv, D_vo, L1, L2):
+    """The Appendix's energy-weighted density matrix W [nmo][nmo], read as the
+    sum of its four printed pieces over the parts of the (p, q) domain they
+    fill:
+      W_pq  = (eps_p + eps_q)/2 D_pq                      every p, q
+            + sum_rs G_pq^rs D^MP2_rs + L'_pq              occupied rows p = i
+            + L''_pq                                       virtual rows p = a
+    with D = D^HF + D^MP2, D^HF the identity on the occupied block (the MO
+    form of sum_i C_imu C_inu), and D^MP2 = D_ij (+) D_ab (+) D_ai (+) D_ia
+    (D_ia = D_ai)."""
+    nocc, nvir = len(eps_occ), len(eps_vir)
+    nmo = nocc + nvir
+    eps = np.concatenate([eps_occ, eps_vir])
+    Dm = np.zeros((nmo, nmo), dtype=np.result_type(Bf, D_oo, D_vv, D_vo))
+    Dm[:nocc, :nocc] = D_oo
+    Dm[nocc:, nocc:] = D_vv
+    Dm[nocc:, :nocc] = D_vo
+    Dm[:nocc, nocc:] = D_vo.T
+    D = Dm.copy()
+    D[:nocc, :nocc] += np.eye(nocc)
+    W = (eps[:, None] + eps[None, :]) / 2.0 * D
+    W[:nocc] += antisym_term(Bf, Dm)[:nocc] + L1
+    W[nocc:] += L2
+    return W
+

@@ -452,3 +452,112 @@ def pin_l_terms_are_orbital_rotation_derivatives(O):
 
 ALL_PINS.extend([pin_gamma_ao_is_ao_derivative, pin_l_terms_are_orbital_rotation_derivatives])
 
+
+def _response_inputs(seed, nocc=2, nvir=3, naux=4, scale=0.1):
+    """Full three-index factor Bf [nmo][nmo][naux] (symmetric in the MO pair),
+    orbital energies, symmetric D_ij and D_ab blocks, and L' / L'' terms."""
+    rng = np.random.default_rng(seed)
+    nmo = nocc + nvir
+    Bf = scale * rng.standard_normal((nmo, nmo, naux))
+    Bf = 0.5 * (Bf + Bf.transpose(1, 0, 2))
+    _, eo, ev = tiny_inputs(nocc, nvir, naux, seed + 1)
+    D_oo = rng.standard_normal((nocc, nocc))
+    D_vv = rng.standard_normal((nvir, nvir))
+    L1 = rng.standard_normal((nocc, nmo))
+    L2 = rng.standard_normal((nvir, nmo))
+    return Bf, eo, ev, D_oo + D_oo.T, D_vv + D_vv.T, L1, L2
+
+
+def _solve_gauss(A, b):
+    """Gauss-Jordan elimination with partial pivoting, pure Python."""
+    n = len(b)
+    M = [list(map(float, A[r])) + [float(b[r])] for r in range(n)]
+    for c in range(n):
+        piv = max(range(c, n), key=lambda r: abs(M[r][c]))
+        M[c], M[piv] = M[piv], M[c]
+        for r in range(n):
+            if r != c:
+                f = M[r][c] / M[c][c]
+                M[r] = [x - f * y for x, y in zip(M[r], M[c])]
+    return [M[r][n] / M[r][r] for r in range(n)]
+
+
+def pin_zvector_brute_force(O):
+    """The antisymmetrised-integral term and the Z-vector solution against
+    pure-Python loops over the Appendix's index forms: G_pq^rs = 2 (pq|rs) -
+    (ps|rq), the right-hand side L''_ai - L'_ia - sum_pq G_ai^pq Dbar_pq, the
+    operator (eps_a - eps_i)/2 D_ai + sum_bj G_ai^bj D_bj, solved by
+    Gauss-Jordan elimination."""
+    nocc, nvir, naux = 2, 3, 4
+    Bf, eo, ev, D_oo, D_vv, L1, L2 = _response_inputs(51, nocc, nvir, naux)
+    nmo = nocc + nvir
+    eri = lambda p, q, r, t: sum(Bf[p, q, P] * Bf[r, t, P] for P in range(naux))
+    G = {(p, q, r, t): 2.0 * eri(p, q, r, t) - eri(p, t, r, q)
+         for p in range(nmo) for q in range(nmo) for r in range(nmo) for t in range(nmo)}
+    D = np.zeros((nmo, nmo))
+    D[:nocc, :nocc], D[nocc:, nocc:] = D_oo, D_vv
+    D[nocc:, :nocc] = np.arange(nvir * nocc).reshape(nvir, nocc) * 0.1   # an ov block for the term alone
+    F = np.array([[sum(G[p, q, r, t] * D[r, t] for r in range(nmo) for t in range(nmo)) for q in range(nmo)]
+                  for p in range(nmo)])
+    assert rel(O.antisym_term(Bf, D), F) <= 1e-12
+    Dbar = np.zeros((nmo, nmo))
+    Dbar[:nocc, :nocc], Dbar[nocc:, nocc:] = D_oo, D_vv
+    rows = [(a, i) for a in range(nvir) for i in range(nocc)]
+    rhs = [L2[a, i] - L1[i, nocc + a] - sum(G[nocc + a, i, p, q] * Dbar[p, q] for p in range(nmo) for q in range(nmo))
+           for a, i in rows]
+    A = [[(ev[a] - eo[i]) / 2.0 * (a == b and i == j) + G[nocc + a, i, nocc + b, j] for b, j in rows] for a, i in rows]
+    want = np.array(_solve_gauss(A, rhs)).reshape(nvir, nocc)
+    assert rel(O.zvector(Bf, eo, ev, D_oo, D_vv, L1, L2), want) <= 1e-11
+
+
+def pin_zvector_single_pair(O):
+    """nocc = nvir = 1: G_ai^ai = 2 (ai|ai) - (ai|ai) = (ai|ai), so
+    D_ai = (L''_ai - L'_ia - sum_pq G_ai^pq Dbar_pq) / ((eps_a - eps_i)/2 + (ai|ai)),
+    with sum_pq G_ai^pq Dbar_pq = [2 (ai|ii) - (ai|ii)] D_ii + [2 (ai|aa) - (aa|ai)] D_aa."""
+    Bf, eo, ev, D_oo, D_vv, L1, L2 = _response_inputs(52, 1, 1, 5)
+    aiai = float(Bf[1, 0] @ Bf[1, 0])
+    aiii = float(Bf[1, 0] @ Bf[0, 0])
+    aiaa = float(Bf[1, 0] @ Bf[1, 1])
+    rhs = L2[0, 0] - L1[0, 1] - (aiii * D_oo[0, 0] + aiaa * D_vv[0, 0])
+    want = rhs / ((ev[0] - eo[0]) / 2.0 + aiai)
+    got = O.zvector(Bf, eo, ev, D_oo, D_vv, L1, L2)
+    assert got.shape == (1, 1) and abs(got[0, 0] - want) <= 1e-13 * max(1.0, abs(want))
+
+
+def pin_energy_weighted_density_hf_limit(O):
+    """With no MP2 density and no L terms, W is the HF energy-weighted
+    density: eps_i on the occupied diagonal, zero elsewhere (the MO form of
+    sum_i eps_i C_imu C_inu).  With them, the occupied rows carry
+    sum_rs G_iq^rs D^MP2_rs + L'_iq and the virtual rows L''_aq on top of
+    (eps_p + eps_q)/2 D_pq, checked against pure-Python loops."""
+    nocc, nvir, naux = 2, 3, 4
+    Bf, eo, ev, D_oo, D_vv, L1, L2 = _response_inputs(53, nocc, nvir, naux)
+    nmo = nocc + nvir
+    z = np.zeros
+    W0 = O.energy_weighted_density(Bf, eo, ev, z((nocc, nocc)), z((nvir, nvir)), z((nvir, nocc)),
+                                   z((nocc, nmo)), z((nvir, nmo)))
+    want = np.zeros((nmo, nmo))
+    want[:nocc, :nocc] = np.diag(eo)
+    assert rel(W0, want) <= 1e-15
+    D_vo = np.random.default_rng(54).standard_normal((nvir, nocc))
+    W = O.energy_weighted_density(Bf, eo, ev, D_oo, D_vv, D_vo, L1, L2)
+    eps = list(eo) + list(ev)
+    Dm = np.zeros((nmo, nmo))
+    Dm[:nocc, :nocc], Dm[nocc:, nocc:], Dm[nocc:, :nocc], Dm[:nocc, nocc:] = D_oo, D_vv, D_vo, D_vo.T
+    eri = lambda p, q, r, t: sum(Bf[p, q, P] * Bf[r, t, P] for P in range(naux))
+    ref = np.zeros((nmo, nmo))
+    for p in range(nmo):
+        for q in range(nmo):
+            d = Dm[p, q] + (1.0 if (p == q and p < nocc) else 0.0)
+            w = (eps[p] + eps[q]) / 2.0 * d
+            if p < nocc:
+                w += sum((2.0 * eri(p, q, r, t) - eri(p, t, r, q)) * Dm[r, t] for r in range(nmo) for t in range(nmo))
+                w += L1[p, q]
+            else:
+                w += L2[p - nocc, q]
+            ref[p, q] = w
+    assert rel(W, ref) <= 1e-12
+
+
+ALL_PINS.extend([pin_zvector_brute_force, pin_zvector_single_pair, pin_energy_weighted_density_hf_limit])
+

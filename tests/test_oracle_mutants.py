@@ -54,6 +54,15 @@ MUTANTS = [
     ("l_dprime aux index not matched", 'np.einsum("iaP,iqP->aq", Gamma, I_iq)', 'np.einsum("iaP,iqQ->aq", Gamma, I_iq)'),
     ("l_dprime occupied index not matched", 'np.einsum("iaP,iqP->aq", Gamma, I_iq)',
      'np.einsum("iaP,jqP->aq", Gamma, I_iq)'),
+    ("antisymmetrised term exchange indices", 'exchange = np.einsum("psP,rqP,rs->pq", Bf, Bf, D)',
+     'exchange = np.einsum("pqP,rsP,rs->pq", Bf, Bf, D)'),
+    ("Z-vector operator exchange indices", 'exchange = np.einsum("ajP,biP->aibj", Bvo, Bvo)',
+     'exchange = np.einsum("aiP,bjP->aibj", Bvo, Bvo)'),
+    ("Z-vector orbital energy gap sign", "np.diag(((eps_vir[:, None] - eps_occ[None, :]) / 2.0)",
+     "np.diag(((eps_occ[None, :] - eps_vir[:, None]) / 2.0)"),
+    ("Z-vector L' transposed", "rhs = L2[:, :nocc] - L1[:, nocc:].T", "rhs = L2[:, :nocc] - L2[:, :nocc]"),
+    ("W misses the HF density", "D[:nocc, :nocc] += np.eye(nocc)", "D[:nocc, :nocc] += 0.0"),
+    ("W puts L'' on the occupied rows", "W[nocc:] += L2", "W[nocc:] += 0.0"),
     ("skip mask read one way only", "(skip[k][j] or skip[j][k])", "skip[k][j]"),
     ("skipped pair still computed", "continue            # screened out", "pass            # screened out"),
     ("pair_energy uses X", "V, X, T = pair_quantities(B, eps_occ, eps_vir, i, j)\n    return np.sum(T * V)",

@@ -11,6 +11,10 @@ Pin status of every oracle function:
   gamma_metric                chain rule: dE/dB3 = 4 gamma_metric (complex step)
   gamma_ao                    chain rule through the MO transform (complex step)
   l_prime, l_dprime           orbital-mixing derivatives of E (complex step)
+  antisym_term, zvector       brute force over the Appendix's index forms
+                              (Gauss-Jordan solve), single-pair closed form
+  energy_weighted_density     HF limit (eps_i on the occupied diagonal) and
+                              brute force over the pieces as read
 No function is unpinned.
 """
 import pytest
