@@ -141,6 +141,37 @@ int rimp2_fragment(int32_t nocc, int32_t nvir, int32_t naux,
                    const rimp2_opts* opts, void* stream);
 
 /*
+ * rimp2_fragment without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * The scratch space is a fixed array of RIMP2_NOALLOC_SCRATCH_BYTES (256 MiB)
+ * inside the library's device code: each GPU that runs the library holds its
+ * own copy from the first call on that device until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree, events or host tables): its
+ * plan takes the largest slab group whose workspace fits the array (or
+ * opts->slab_group when given), and a fragment whose workspace does not fit
+ * even with one occupied orbital per group returns RIMP2_ENOMEM.
+ * opts->autotune is not available here (RIMP2_ENOTSUP), and the timing of
+ * rimp2_timing_enable records nothing for this call.
+ *
+ * Every call on one GPU shares that GPU's array and finds the previous
+ * call's contents in it; no kernel relies on its initial contents (every
+ * word is written before it is read within a call).  Calls that overlap on
+ * one GPU -- on different streams, or from different host threads -- race
+ * on the array and give undefined results: serialise them.
+ *
+ *   status_dev  device, write [1] or NULL: receives the call's device status
+ *               (RIMP2_OK or RIMP2_EGAP) when the stream reaches the end of
+ *               the call; the other arguments are those of rimp2_fragment.
+ */
+#define RIMP2_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int rimp2_fragment_noalloc(int32_t nocc, int32_t nvir, int32_t naux,
+                           const double* B, const double* eps_occ, const double* eps_vir,
+                           double* E, double* Gamma, double* P_ij, double* P_ab, double* e_pair,
+                           int32_t* status_dev, const rimp2_opts* opts, void* stream);
+
+/*
  * Read the device status word of the last call that used this workspace
  * (synchronises `stream` first).  Writes RIMP2_OK or RIMP2_EGAP to *status.
  */

@@ -40,6 +40,15 @@
 
 using namespace rimp2;
 
+// Scratch space of rimp2_fragment_noalloc: one array per GPU, part of the
+// library's code object, so each device that runs the library holds its own
+// copy until the process ends.  Host code never uses the name `scratch` as an
+// address: rimp2_fragment_noalloc takes the device address from
+// hipGetSymbolAddress once per device (with that device current) and passes
+// it to the kernels as the workspace.
+constexpr size_t kScratchBytes = (size_t)RIMP2_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 
@@ -66,6 +75,10 @@ Tracer& tracer() {
   return t;
 }
 
+// Set while this thread runs rimp2_fragment_noalloc: no events are created
+// or recorded (that entry point allocates nothing).
+thread_local bool t_noalloc = false;
+
 // Launches `launch` on stream st; while timing is on, brackets it with events.
 template <class F>
 int traced(int role, double af, double ef, double ab, hipStream_t st, F&& launch) {
@@ -74,7 +87,7 @@ int traced(int role, double af, double ef, double ab, hipStream_t st, F&& launch
   bool on;
   {
     std::lock_guard<std::mutex> lk(T.mu);
-    on = T.on;
+    on = T.on && !t_noalloc;
     for (int i = 0; on && i < 2; ++i) {
       if (!T.pool.empty()) {
         ev[i] = T.pool.back();
@@ -827,6 +840,56 @@ int want_of(const double* Gam, const double* Pij, const double* Pab, int* want) 
 }
 
 
+// ---- scratch space of the entry point that allocates nothing ----------------
+// The array `scratch` is declared at file scope at the top of this file.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RIMP2_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(RIMP2_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return RIMP2_OK;
+}
+
+// The plan of rimp2_fragment_noalloc: the caller's options with, unless the
+// caller fixed the slab group, the largest slab budget whose workspace fits
+// the scratch array.
+int noalloc_plan(int64_t nocc, int64_t nvir, int64_t naux, int want, const rimp2_opts* opts, Plan* P) {
+  rimp2_opts o{};
+  if (opts) o = *opts;
+  if (o.autotune) return fail(RIMP2_ENOTSUP, "autotuning records events: not available without allocation");
+  int rc;
+  if (o.slab_group == 0) {
+    o.slab_budget_bytes = kScratchBytes;
+    for (int it = 0; it < 64; ++it) {
+      if ((rc = make_plan(nocc, nvir, naux, want & RIMP2_WANT_GAMMA, want & RIMP2_WANT_DENSITY, &o, P))) return rc;
+      if (P->total <= kScratchBytes) return RIMP2_OK;
+      const size_t over = P->total - kScratchBytes;
+      if (o.slab_budget_bytes <= over + 1) break;
+      o.slab_budget_bytes -= over + 1;   // the slabs shrink by at least the overshoot (or g reaches 1)
+    }
+  }
+  if ((rc = make_plan(nocc, nvir, naux, want & RIMP2_WANT_GAMMA, want & RIMP2_WANT_DENSITY, &o, P))) return rc;
+  if (P->total > kScratchBytes)
+    return fail(RIMP2_ENOMEM, "fragment nocc=%lld nvir=%lld naux=%lld needs %zu bytes of scratch, more than the "
+                "%zu of rimp2_fragment_noalloc", (long long)nocc, (long long)nvir, (long long)naux, P->total,
+                kScratchBytes);
+  return RIMP2_OK;
+}
+
+
 // ---- batches -----------------------------------------------------------------
 // Grouped GEMM lists of a wave: 4 roles x 2 candidate tiles x 4 loaders
 // (0: two chunks ahead, 1: the same with runs ending inside chunks, 2: the
@@ -1265,6 +1328,29 @@ int rimp2_fragment(int32_t nocc, int32_t nvir, int32_t naux, const double* B, co
     return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, P.total);
   return run_fragment(P, B, eps_occ, eps_vir, E, Gamma, P_ij, P_ab, e_pair, (char*)workspace,
                       opts ? opts->pair_skip : nullptr, (hipStream_t)stream);
+}
+
+int rimp2_fragment_noalloc(int32_t nocc, int32_t nvir, int32_t naux, const double* B, const double* eps_occ,
+                           const double* eps_vir, double* E, double* Gamma, double* P_ij, double* P_ab,
+                           double* e_pair, int32_t* status_dev, const rimp2_opts* opts, void* stream) {
+  if (!B || !eps_occ || !eps_vir || !E) return fail(RIMP2_EINVAL, "B, eps_occ, eps_vir and E must not be NULL");
+  int want, rc;
+  if ((rc = want_of(Gamma, P_ij, P_ab, &want))) return rc;
+  Plan P;
+  if ((rc = noalloc_plan(nocc, nvir, naux, want, opts, &P))) return rc;
+  char* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  t_noalloc = true;
+  rc = run_fragment(P, B, eps_occ, eps_vir, E, Gamma, P_ij, P_ab, e_pair, ws, opts ? opts->pair_skip : nullptr, st);
+  if (rc == RIMP2_OK && status_dev) {
+    rc = traced(R_STATUS, 0, 0, 8.0, st, [&] {
+      hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, st, (const int32_t*)(ws + P.off_status),
+                         status_dev, 0);
+    });
+  }
+  t_noalloc = false;
+  return rc;
 }
 
 int rimp2_read_status(const void* workspace, void* stream, int32_t* status) {
