@@ -58,7 +58,8 @@ typedef enum {
   RIMP2_EWORKSPACE = -3, /* workspace pointer misaligned (needs 256 B) */
   RIMP2_EDEVICE = -4,    /* a HIP runtime call failed (message says which) */
   RIMP2_EGAP = -5,       /* device: max eps_occ >= min eps_vir, or NaN eps */
-  RIMP2_ENOTSUP = -6     /* option combination not supported */
+  RIMP2_ENOTSUP = -6,    /* option combination not supported */
+  RIMP2_ENOCONV = -7     /* an iterative solve stopped before its tolerance */
 } rimp2_status;
 
 /* Arithmetic of the two large contractions, (ia|jb) and Gamma. */

@@ -54,11 +54,11 @@ namespace {
 
 // ---- kernel timing -------------------------------------------------------
 enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
-            R_GAMMA_T, R_GAMMA_AO, R_LTERM, R_NROLES };
+            R_GAMMA_T, R_GAMMA_AO, R_LTERM, R_RESPONSE, R_NROLES };
 const char* const kRoleName[R_NROLES] = {"gap_check",  "ints_gemm",     "amplitude",  "gamma_gemm",
                                          "pab_gemm",   "pij_gemm",      "splitk_reduce", "energy_sum",
                                          "status_copy", "digit_split", "ints_oz8",   "gamma_oz8",
-                                         "gamma_t_gemm", "gamma_ao_gemm", "l_terms_gemm"};
+                                         "gamma_t_gemm", "gamma_ao_gemm", "l_terms_gemm", "response"};
 struct TraceRec {
   int role;
   hipEvent_t e0, e1;
@@ -1299,6 +1299,7 @@ const char* rimp2_status_string(int s) {
     case RIMP2_EDEVICE: return "RIMP2_EDEVICE";
     case RIMP2_EGAP: return "RIMP2_EGAP";
     case RIMP2_ENOTSUP: return "RIMP2_ENOTSUP";
+    case RIMP2_ENOCONV: return "RIMP2_ENOCONV";
     default: return "unknown rimp2 status";
   }
 }
@@ -1626,6 +1627,429 @@ int rimp2_l_terms(int32_t nocc, int32_t nvir, int32_t nmo, int32_t naux, const d
     if ((rc = run(gp, lp.s2, L2, 2.0 * v * q * o * x, 8.0 * (v + q) * o * x + 8.0 * v * q))) return rc;
   }
   return RIMP2_OK;
+}
+
+// ---- orbital response: antisymmetrised-integral term, Z-vector, W ---------------
+namespace {
+
+// c_part[z][P] = sum over (r, s) pairs of chunk z of Bf[r][s][P] D[r][s]
+// (fixed chunking: deterministic after the ordered reduction).
+__global__ __launch_bounds__(256) void coulomb_vector_kernel(const double* Bf, const double* D, int64_t npairs,
+                                                             int64_t naux, int64_t chunk, double* part,
+                                                             const int32_t* status) {
+  if (*status != 0) return;
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x, z = blockIdx.y;
+  if (P >= naux) return;
+  const int64_t rs0 = z * chunk, rs1 = min(npairs, rs0 + chunk);
+  double s = 0.0;
+  for (int64_t rs = rs0; rs < rs1; ++rs) s += Bf[rs * naux + P] * D[rs];
+  part[z * naux + P] = s;
+}
+
+// out[p][q] = 2 sum_P Bf[p][q][P] c[P] - K[p][q] for p < nrows (rows r0..),
+// q < ncols (columns c0..); one wave per (p, q), lanes over P, fixed-order
+// wave reduction.
+__global__ __launch_bounds__(256) void antisym_combine_kernel(const double* Bf, int64_t nmo, int64_t naux,
+                                                              int64_t r0, int64_t nrows, int64_t c0, int64_t ncols,
+                                                              const double* c, const double* K, double* F,
+                                                              int64_t ldf, const int32_t* status) {
+  if (*status != 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= nrows * ncols) return;
+  const int64_t p = e / ncols, q = e - p * ncols;
+  const double* row = Bf + ((r0 + p) * nmo + c0 + q) * naux;
+  double s = 0.0;
+  for (int64_t P = lane; P < naux; P += 64) s += row[P] * c[P];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) F[p * ldf + q] = 2.0 * s - K[p * ncols + q];
+}
+
+struct AntisymPlan {
+  int64_t nmo, naux, nrows, ncols, chunks, chunk, s_k;
+  size_t off_status, off_cpart, off_c, off_Y, off_Kp, off_K, total;
+};
+
+AntisymPlan antisym_plan(int64_t nmo, int64_t naux, int64_t nrows, int64_t ncols) {
+  AntisymPlan A{};
+  A.nmo = nmo; A.naux = naux; A.nrows = nrows; A.ncols = ncols;
+  const int64_t npairs = nmo * nmo;
+  A.chunks = std::max<int64_t>(1, std::min<int64_t>(256, npairs / 64));
+  A.chunk = cdiv(npairs, A.chunks);
+  A.chunks = cdiv(npairs, A.chunk);
+  A.s_k = choose_splits(cdiv(nrows, kTile) * cdiv(ncols, kTile), nmo * naux);
+  size_t off = 0;
+  A.off_status = off; off = align_up(off + 64);
+  A.off_cpart = off; off = align_up(off + 8 * (size_t)A.chunks * naux);
+  A.off_c = off; off = align_up(off + 8 * (size_t)naux);
+  A.off_Y = off; off = align_up(off + 8 * (size_t)nmo * ncols * naux);
+  A.off_Kp = off; off = align_up(off + 8 * (size_t)A.s_k * nrows * ncols);
+  A.off_K = off; off = align_up(off + 8 * (size_t)nrows * ncols);
+  A.total = off;
+  return A;
+}
+
+// F[p - r0][q - c0] (row stride ldf) = sum_rs G_pq^rs D_rs for the rows
+// [r0, r0 + nrows) and columns [c0, c0 + ncols), with G_pq^rs = 2 (pq|rs) -
+// (ps|rq) and (pq|rs) = sum_P Bf[p][q][P] Bf[r][s][P]:
+//   Coulomb  2 sum_P Bf[p][q][P] c_P,   c_P = sum_rs Bf[r][s][P] D_rs
+//   exchange sum_(s,P) Bf[p][s][P] Y[s][q][P],   Y[s][q][P] = sum_r D_rs Bf[r][q][P]
+// The workspace's status word must be zero (the callers clear it).
+int antisym_run(const AntisymPlan& A, const double* Bf, const double* D, int64_t r0, int64_t c0, double* F,
+                int64_t ldf, char* ws, hipStream_t st) {
+  const int64_t nmo = A.nmo, naux = A.naux, nrows = A.nrows, ncols = A.ncols;
+  const int32_t* status = (const int32_t*)(ws + A.off_status);
+  double* cpart = (double*)(ws + A.off_cpart);
+  double* c = (double*)(ws + A.off_c);
+  double* Y = (double*)(ws + A.off_Y);
+  double* Kp = (double*)(ws + A.off_Kp);
+  double* K = (double*)(ws + A.off_K);
+  int rc;
+  if ((rc = traced(R_RESPONSE, 0, 0, 8.0 * nmo * nmo * (naux + 1), st, [&] {
+         hipLaunchKernelGGL(coulomb_vector_kernel, dim3((unsigned)cdiv(naux, 256), (unsigned)A.chunks), dim3(256), 0,
+                            st, Bf, D, nmo * nmo, naux, A.chunk, cpart, status);
+         hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, c, naux,
+                            (const double*)cpart, naux, naux, (int)A.chunks, (int64_t)1, naux, 1.0, 0, status);
+       })))
+    return rc;
+  {  // Y[s][(q, P)] = sum_r D[r][s] Bf[r][c0 + q][P]
+    GemmParams gp{};
+    gp.M = nmo; gp.N = ncols * naux; gp.K = nmo; gp.kchunk = nmo;
+    gp.Am = NOperand{D, nmo};
+    gp.Bn = NOperand{Bf + c0 * naux, nmo * naux};
+    gp.C = Y; gp.ldc = ncols * naux; gp.status = status;
+    if ((rc = launch_gemm<128, 128, true, ROLE_AO, false>(gp, st, R_RESPONSE, 2.0 * nmo * nmo * ncols * naux,
+                                                           8.0 * (nmo * nmo + 2.0 * nmo * ncols * naux), false)))
+      return rc;
+  }
+  {  // K[p][q] = sum over (s, P) of Bf[r0 + p][s][P] Y[s][q][P]
+    GemmParams gp{};
+    gp.M = nrows; gp.N = ncols; gp.K = nmo * naux;
+    gp.kchunk = cdiv(gp.K, A.s_k);
+    gp.A = kop(Bf + r0 * nmo * naux, nmo * naux, INT64_MAX, 0);
+    gp.Bk = kop(Y, naux, naux, ncols * naux);
+    gp.C = Kp; gp.ldc = ncols; gp.split_stride = nrows * ncols; gp.status = status;
+    const int64_t splits = cdiv(gp.K, cdiv(gp.kchunk, kBK) * kBK);
+    if ((rc = launch_gemm<128, 128, false, ROLE_LTERM, false>(gp, st, R_RESPONSE, 2.0 * nrows * ncols * nmo * naux,
+                                                               8.0 * (nrows + ncols) * nmo * naux, false)))
+      return rc;
+    const int64_t n = nrows * ncols;
+    if ((rc = traced(R_REDUCE, 0, 0, 8.0 * (splits + 1) * n, st, [&] {
+           hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, K, ncols,
+                              (const double*)Kp, ncols, n, (int)splits, nrows, ncols, 1.0, 0, status);
+         })))
+      return rc;
+  }
+  return traced(R_RESPONSE, 0, 0, 8.0 * nrows * ncols * (naux + 2), st, [&] {
+    hipLaunchKernelGGL(antisym_combine_kernel, dim3((unsigned)cdiv(nrows * ncols, 4)), dim3(256), 0, st, Bf, nmo, naux,
+                       r0, nrows, c0, ncols, (const double*)c, (const double*)K, F, ldf, status);
+  });
+}
+
+// D[nmo][nmo]: the blocks given (any may be null: zero); the occupied-virtual
+// block is the transpose of D_vo when ov != 0, else zero; hf adds the
+// identity on the occupied block.
+__global__ __launch_bounds__(256) void assemble_density_kernel(int64_t nocc, int64_t nvir, const double* Doo,
+                                                               const double* Dvv, const double* Dvo, int ov, int hf,
+                                                               double* D) {
+  const int64_t nmo = nocc + nvir, e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nmo * nmo) return;
+  const int64_t p = e / nmo, q = e - p * nmo;
+  double v = 0.0;
+  if (p < nocc && q < nocc) v = Doo ? Doo[p * nocc + q] : 0.0;
+  else if (p >= nocc && q >= nocc) v = Dvv ? Dvv[(p - nocc) * nvir + (q - nocc)] : 0.0;
+  else if (p >= nocc) v = Dvo ? Dvo[(p - nocc) * nocc + q] : 0.0;
+  else v = (Dvo && ov) ? Dvo[(q - nocc) * nocc + p] : 0.0;
+  if (hf && p == q && p < nocc) v += 1.0;
+  D[e] = v;
+}
+
+// Z-vector pieces, element (a, i) of [nvir][nocc].
+//   mode 0: out = L2[a][i] - L1[i][nocc + a] - F[a][i]                (right-hand side)
+//   mode 1: out = (eps_a - eps_i)/2 x[a][i] + F[a][i]                 (operator)
+//   mode 2: out = (eps_a - eps_i)/2 + sum_P Bf[nocc+a][i][P]^2        (diagonal)
+__global__ __launch_bounds__(256) void zvector_elem_kernel(int mode, int64_t nocc, int64_t nvir, int64_t naux,
+                                                           const double* eo, const double* ev, const double* Bf,
+                                                           const double* L1, const double* L2, const double* x,
+                                                           const double* F, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nocc * nvir) return;
+  const int64_t a = e / nocc, i = e - a * nocc, nmo = nocc + nvir;
+  const double gap = (ev[a] - eo[i]) / 2.0;
+  if (mode == 0) {
+    out[e] = (L2[a * nmo + i] - L1[i * nmo + nocc + a]) - F[e];
+  } else if (mode == 1) {
+    out[e] = gap * x[e] + F[e];
+  } else {
+    const double* row = Bf + ((nocc + a) * nmo + i) * naux;
+    double s = 0.0;
+    for (int64_t P = 0; P < naux; ++P) s += row[P] * row[P];
+    out[e] = gap + s;
+  }
+}
+
+// Sum over n of u[n] v[n] (w == null) or of u[n] v[n] / w[n], one workgroup,
+// fixed order; written to out[0].
+__global__ __launch_bounds__(256) void dot_kernel(const double* u, const double* v, const double* w, int64_t n,
+                                                  double* out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) s += w ? u[k] * v[k] / w[k] : u[k] * v[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int wdt = 128; wdt > 0; wdt >>= 1) {
+    if (threadIdx.x < wdt) sh[threadIdx.x] += sh[threadIdx.x + wdt];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// CG vector updates.
+//   mode 0: y = u / w                       (preconditioned residual; initial guess)
+//   mode 1: x += alpha p; r -= alpha q      (u = p, v = q, y = x, z = r)
+//   mode 2: p = r / w + beta p              (u = r, y = p)
+//   mode 3: y = u - v                       (initial residual)
+__global__ __launch_bounds__(256) void cg_update_kernel(int mode, int64_t n, double alpha, const double* u,
+                                                        const double* v, const double* w, double* y, double* z) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  if (mode == 0) y[k] = u[k] / w[k];
+  else if (mode == 1) { y[k] += alpha * u[k]; z[k] -= alpha * v[k]; }
+  else if (mode == 2) y[k] = u[k] / w[k] + alpha * y[k];
+  else y[k] = u[k] - v[k];
+}
+
+// W[p][q] = (eps_p + eps_q)/2 D[p][q] + (p < nocc ? F[p][q] + L1[p][q] : L2[p - nocc][q]),
+// D including the HF identity on the occupied block.
+__global__ __launch_bounds__(256) void w_assemble_kernel(int64_t nocc, int64_t nvir, const double* eo,
+                                                         const double* ev, const double* D, const double* F,
+                                                         const double* L1, const double* L2, double* W) {
+  const int64_t nmo = nocc + nvir, e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nmo * nmo) return;
+  const int64_t p = e / nmo, q = e - p * nmo;
+  const double ep = p < nocc ? eo[p] : ev[p - nocc], eq = q < nocc ? eo[q] : ev[q - nocc];
+  double w = (ep + eq) / 2.0 * D[e];
+  w += p < nocc ? F[e] + L1[e] : L2[(p - nocc) * nmo + q];
+  W[e] = w;
+}
+
+struct ZPlan {
+  AntisymPlan A;
+  size_t off_D, off_F, off_rhs, off_diag, off_x, off_r, off_p, off_q, off_dot, total;
+};
+
+ZPlan zvector_plan(int64_t nocc, int64_t nvir, int64_t naux) {
+  ZPlan Z{};
+  const int64_t nmo = nocc + nvir, nov = nocc * nvir;
+  Z.A = antisym_plan(nmo, naux, nvir, nocc);
+  size_t off = Z.A.total;
+  Z.off_D = off; off = align_up(off + 8 * (size_t)nmo * nmo);
+  Z.off_F = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_rhs = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_diag = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_x = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_r = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_p = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_q = off; off = align_up(off + 8 * (size_t)nov);
+  Z.off_dot = off; off = align_up(off + 64);
+  Z.total = off;
+  return Z;
+}
+
+int response_sizes(int32_t nocc, int32_t nvir, int32_t naux) {
+  if (nocc < 1 || nvir < 1 || naux < 1) return fail(RIMP2_EINVAL, "sizes must be >= 1");
+  const double nmo = (double)nocc + nvir;
+  if (nmo * nmo * naux >= 4.6e18 || nmo > (1 << 20)) return fail(RIMP2_EINVAL, "sizes too large");
+  return RIMP2_OK;
+}
+
+int clear_status(char* ws, hipStream_t st) {
+  return traced(R_STATUS, 0, 0, 8.0, st, [&] {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, (unsigned long long*)ws, 1);
+  });
+}
+
+int read_dot(const double* d, double* h, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return RIMP2_OK;
+}
+
+}  // namespace
+
+int rimp2_antisym_workspace_size(int32_t nmo, int32_t naux, int32_t nrows, int32_t ncols, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  if (nmo < 1 || naux < 1 || nrows < 1 || ncols < 1) return fail(RIMP2_EINVAL, "sizes must be >= 1");
+  *bytes = antisym_plan(nmo, naux, nrows, ncols).total;
+  return RIMP2_OK;
+}
+
+int rimp2_antisym_term(int32_t nmo, int32_t naux, int32_t r0, int32_t nrows, int32_t c0, int32_t ncols,
+                       const double* Bf, const double* D, double* F, int64_t ldf, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+  if (nmo < 1 || naux < 1 || nrows < 1 || ncols < 1 || r0 < 0 || c0 < 0 || (int64_t)r0 + nrows > nmo ||
+      (int64_t)c0 + ncols > nmo || ldf < ncols)
+    return fail(RIMP2_EINVAL, "rows [r0, r0 + nrows) and columns [c0, c0 + ncols) must lie in [0, nmo), ldf >= ncols");
+  if (!Bf || !D || !F || !workspace) return fail(RIMP2_EINVAL, "Bf, D, F and workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  const AntisymPlan A = antisym_plan(nmo, naux, nrows, ncols);
+  if (workspace_bytes < A.total) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, A.total);
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = clear_status((char*)workspace, st))) return rc;
+  return antisym_run(A, Bf, D, r0, c0, F, ldf, (char*)workspace, st);
+}
+
+int rimp2_zvector_workspace_size(int32_t nocc, int32_t nvir, int32_t naux, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  int rc;
+  if ((rc = response_sizes(nocc, nvir, naux))) return rc;
+  *bytes = zvector_plan(nocc, nvir, naux).total;
+  return RIMP2_OK;
+}
+
+int rimp2_zvector(int32_t nocc, int32_t nvir, int32_t naux, const double* Bf, const double* eps_occ,
+                  const double* eps_vir, const double* P_ij, const double* P_ab, const double* L1, const double* L2,
+                  double* D_ai, double tol, int32_t max_iter, int32_t* iterations, double* rel_residual,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+  int rc;
+  if ((rc = response_sizes(nocc, nvir, naux))) return rc;
+  if (!Bf || !eps_occ || !eps_vir || !P_ij || !P_ab || !L1 || !L2 || !D_ai || !workspace)
+    return fail(RIMP2_EINVAL, "Bf, eps_occ, eps_vir, P_ij, P_ab, L1, L2, D_ai and workspace must not be NULL");
+  if (!(tol > 0.0) || max_iter < 1) return fail(RIMP2_EINVAL, "tol must be > 0 and max_iter >= 1");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  const ZPlan Z = zvector_plan(nocc, nvir, naux);
+  if (workspace_bytes < Z.total) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, Z.total);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const int64_t no = nocc, nv = nvir, na = naux, nmo = no + nv, nov = no * nv;
+  double* D = (double*)(ws + Z.off_D);
+  double* F = (double*)(ws + Z.off_F);
+  double* rhs = (double*)(ws + Z.off_rhs);
+  double* diag = (double*)(ws + Z.off_diag);
+  double* r = (double*)(ws + Z.off_r);
+  double* pv = (double*)(ws + Z.off_p);
+  double* q = (double*)(ws + Z.off_q);
+  double* dot = (double*)(ws + Z.off_dot);
+  double* x = D_ai;
+  const unsigned gn = (unsigned)cdiv(nov, 256), gd = (unsigned)cdiv(nmo * nmo, 256);
+  auto elem = [&](int mode, const double* xin, double* out) {
+    return traced(R_RESPONSE, 0, 0, 8.0 * 3 * nov, st, [&] {
+      hipLaunchKernelGGL(zvector_elem_kernel, dim3(gn), dim3(256), 0, st, mode, no, nv, na, eps_occ, eps_vir, Bf, L1,
+                         L2, xin, (const double*)F, out);
+    });
+  };
+  auto density = [&](const double* Doo, const double* Dvv, const double* Dvo) {
+    return traced(R_RESPONSE, 0, 0, 8.0 * nmo * nmo, st, [&] {
+      hipLaunchKernelGGL(assemble_density_kernel, dim3(gd), dim3(256), 0, st, no, nv, Doo, Dvv, Dvo, 0, 0, D);
+    });
+  };
+  // out = (eps_a - eps_i)/2 v_ai + sum_bj G_ai^bj v_bj (only the (b, j) block of D holds v)
+  auto apply = [&](const double* v, double* out) -> int {
+    int r2;
+    if ((r2 = density(nullptr, nullptr, v))) return r2;
+    if ((r2 = antisym_run(Z.A, Bf, D, no, 0, F, no, ws, st))) return r2;
+    return elem(1, v, out);
+  };
+  auto dotp = [&](const double* u, const double* v, const double* w, double* h) -> int {
+    int r2;
+    if ((r2 = traced(R_RESPONSE, 0, 0, 16.0 * nov, st, [&] {
+           hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(256), 0, st, u, v, w, nov, dot);
+         })))
+      return r2;
+    return read_dot(dot, h, st);
+  };
+  auto update = [&](int mode, double alpha, const double* u, const double* v, const double* w, double* y,
+                    double* z) {
+    return traced(R_RESPONSE, 0, 0, 8.0 * 4 * nov, st, [&] {
+      hipLaunchKernelGGL(cg_update_kernel, dim3(gn), dim3(256), 0, st, mode, nov, alpha, u, v, w, y, z);
+    });
+  };
+  if ((rc = clear_status(ws, st))) return rc;
+  // right-hand side: L''_ai - L'_ia - sum_pq G_ai^pq Dbar_pq, Dbar = D_ij (+) D_ab
+  if ((rc = density(P_ij, P_ab, nullptr))) return rc;
+  if ((rc = antisym_run(Z.A, Bf, D, no, 0, F, no, ws, st))) return rc;
+  if ((rc = elem(0, nullptr, rhs))) return rc;
+  if ((rc = elem(2, nullptr, diag))) return rc;   // Jacobi preconditioner: the operator's diagonal
+  // preconditioned conjugate gradients from x = rhs / diag
+  double bb = 0.0, rz = 0.0, rr = 0.0;
+  if ((rc = dotp(rhs, rhs, nullptr, &bb))) return rc;
+  if ((rc = update(0, 0.0, rhs, nullptr, diag, x, nullptr))) return rc;
+  if ((rc = apply(x, q))) return rc;
+  if ((rc = update(3, 0.0, rhs, q, nullptr, r, nullptr))) return rc;
+  if ((rc = update(0, 0.0, r, nullptr, diag, pv, nullptr))) return rc;
+  if ((rc = dotp(r, r, diag, &rz))) return rc;
+  if ((rc = dotp(r, r, nullptr, &rr))) return rc;
+  const double target = tol * tol * bb;
+  int it = 0;
+  while (rr > target && it < max_iter) {
+    if ((rc = apply(pv, q))) return rc;
+    double pq = 0.0;
+    if ((rc = dotp(pv, q, nullptr, &pq))) return rc;
+    if (!(pq > 0.0)) break;   // the operator is not positive definite along p
+    const double alpha = rz / pq;
+    if ((rc = update(1, alpha, pv, q, nullptr, x, r))) return rc;
+    double rz_new = 0.0;
+    if ((rc = dotp(r, r, diag, &rz_new))) return rc;
+    if ((rc = dotp(r, r, nullptr, &rr))) return rc;
+    if ((rc = update(2, rz_new / rz, r, nullptr, diag, pv, nullptr))) return rc;
+    rz = rz_new;
+    ++it;
+  }
+  if (iterations) *iterations = it;
+  const double rel_res = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+  if (rel_residual) *rel_residual = rel_res;
+  if (!(rr <= target))
+    return fail(RIMP2_ENOCONV, "Z-vector CG stopped after %d iterations at relative residual %.3e (tol %.3e)", it,
+                rel_res, tol);
+  return RIMP2_OK;
+}
+
+int rimp2_energy_weighted_density_workspace_size(int32_t nocc, int32_t nvir, int32_t naux, size_t* bytes) {
+  if (!bytes) return fail(RIMP2_EINVAL, "bytes is NULL");
+  int rc;
+  if ((rc = response_sizes(nocc, nvir, naux))) return rc;
+  const int64_t nmo = (int64_t)nocc + nvir;
+  const AntisymPlan A = antisym_plan(nmo, naux, nocc, nmo);
+  *bytes = A.total + align_up(8 * (size_t)nmo * nmo) * 2;
+  return RIMP2_OK;
+}
+
+int rimp2_energy_weighted_density(int32_t nocc, int32_t nvir, int32_t naux, const double* Bf, const double* eps_occ,
+                                  const double* eps_vir, const double* P_ij, const double* P_ab, const double* D_ai,
+                                  const double* L1, const double* L2, double* W, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  int rc;
+  if ((rc = response_sizes(nocc, nvir, naux))) return rc;
+  if (!Bf || !eps_occ || !eps_vir || !P_ij || !P_ab || !D_ai || !L1 || !L2 || !W || !workspace)
+    return fail(RIMP2_EINVAL, "Bf, eps_occ, eps_vir, P_ij, P_ab, D_ai, L1, L2, W and workspace must not be NULL");
+  if ((uintptr_t)workspace % kAlign) return fail(RIMP2_EWORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  if ((rc = rimp2_energy_weighted_density_workspace_size(nocc, nvir, naux, &need))) return rc;
+  if (workspace_bytes < need) return fail(RIMP2_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const int64_t no = nocc, nv = nvir, nmo = no + nv;
+  const AntisymPlan A = antisym_plan(nmo, naux, nocc, nmo);
+  double* Dm = (double*)(ws + A.total);
+  double* F = (double*)(ws + A.total + align_up(8 * (size_t)nmo * nmo));
+  const unsigned gd = (unsigned)cdiv(nmo * nmo, 256);
+  if ((rc = clear_status(ws, st))) return rc;
+  // D^MP2 (every block) for the antisymmetrised term of the occupied rows
+  if ((rc = traced(R_RESPONSE, 0, 0, 8.0 * nmo * nmo, st, [&] {
+         hipLaunchKernelGGL(assemble_density_kernel, dim3(gd), dim3(256), 0, st, no, nv, P_ij, P_ab, D_ai, 1, 0, Dm);
+       })))
+    return rc;
+  if ((rc = antisym_run(A, Bf, Dm, 0, 0, F, nmo, ws, st))) return rc;
+  // D = D^HF + D^MP2 for the energy-weighted piece
+  if ((rc = traced(R_RESPONSE, 0, 0, 8.0 * nmo * nmo, st, [&] {
+         hipLaunchKernelGGL(assemble_density_kernel, dim3(gd), dim3(256), 0, st, no, nv, P_ij, P_ab, D_ai, 1, 1, Dm);
+       })))
+    return rc;
+  return traced(R_RESPONSE, 0, 0, 8.0 * 4 * nmo * nmo, st, [&] {
+    hipLaunchKernelGGL(w_assemble_kernel, dim3(gd), dim3(256), 0, st, no, nv, eps_occ, eps_vir, (const double*)Dm,
+                       (const double*)F, L1, L2, W);
+  });
 }
 
 }  // extern "C"

@@ -26,6 +26,20 @@ def _L():
         L.rimp2_l_terms_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
         L.rimp2_l_terms.restype = ctypes.c_int
         L.rimp2_l_terms.argtypes = [i32] * 4 + [vp] * 6 + [sz, vp]
+        i64, dbl = ctypes.c_int64, ctypes.c_double
+        L.rimp2_antisym_workspace_size.restype = ctypes.c_int
+        L.rimp2_antisym_workspace_size.argtypes = [i32] * 4 + [ctypes.POINTER(sz)]
+        L.rimp2_antisym_term.restype = ctypes.c_int
+        L.rimp2_antisym_term.argtypes = [i32] * 6 + [vp, vp, vp, i64, vp, sz, vp]
+        L.rimp2_zvector_workspace_size.restype = ctypes.c_int
+        L.rimp2_zvector_workspace_size.argtypes = [i32] * 3 + [ctypes.POINTER(sz)]
+        L.rimp2_zvector.restype = ctypes.c_int
+        L.rimp2_zvector.argtypes = [i32] * 3 + [vp] * 8 + [dbl, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp, sz,
+                                                           vp]
+        L.rimp2_energy_weighted_density_workspace_size.restype = ctypes.c_int
+        L.rimp2_energy_weighted_density_workspace_size.argtypes = [i32] * 3 + [ctypes.POINTER(sz)]
+        L.rimp2_energy_weighted_density.restype = ctypes.c_int
+        L.rimp2_energy_weighted_density.argtypes = [i32] * 3 + [vp] * 9 + [vp, sz, vp]
         _bound = True
     return L
 
@@ -94,3 +108,62 @@ def l_terms(Gamma: torch.Tensor, I_qa: Optional[torch.Tensor], I_iq: Optional[to
     _check(L.rimp2_l_terms(nocc, nvir, nmo, naux, _ptr(Gamma), _ptr(I_qa), _ptr(I_iq), _ptr(L1), _ptr(L2),
                            _ptr(workspace), workspace.numel(), _stream_handle(stream)))
     return L1, L2
+
+
+def _ws(size_fn, *args, device):
+    n = ctypes.c_size_t(0)
+    _check(size_fn(*args, ctypes.byref(n)))
+    return torch.empty(n.value, dtype=torch.uint8, device=device)
+
+
+def antisym_term(Bf: torch.Tensor, D: torch.Tensor, rows=None, cols=None, stream=None) -> torch.Tensor:
+    """F[p, q] = sum_rs G_pq^rs D[r, s] for p in range(*rows), q in range(*cols)
+    (default: every MO) on the GPU (rimp2_antisym_term)."""
+    nmo, nmo2, naux = Bf.shape
+    if nmo2 != nmo:
+        raise ValueError("Bf must be [nmo][nmo][naux]")
+    _need(Bf, (nmo, nmo, naux), "Bf")
+    _need(D, (nmo, nmo), "D")
+    r0, r1 = rows if rows is not None else (0, nmo)
+    c0, c1 = cols if cols is not None else (0, nmo)
+    F = torch.empty((r1 - r0, c1 - c0), dtype=torch.float64, device=Bf.device)
+    L = _L()
+    ws = _ws(L.rimp2_antisym_workspace_size, nmo, naux, r1 - r0, c1 - c0, device=Bf.device)
+    _check(L.rimp2_antisym_term(nmo, naux, r0, r1 - r0, c0, c1 - c0, _ptr(Bf), _ptr(D), _ptr(F), c1 - c0, _ptr(ws),
+                                ws.numel(), _stream_handle(stream)))
+    return F
+
+
+def zvector(Bf, eps_occ, eps_vir, P_ij, P_ab, L1, L2, tol: float = 1e-12, max_iter: int = 500, stream=None):
+    """(D_ai [nvir][nocc], iterations, relative residual) from the Z-vector
+    equation on the GPU (rimp2_zvector); raises Rimp2Error(RIMP2_ENOCONV)
+    when CG does not reach tol."""
+    nocc, nvir = eps_occ.shape[0], eps_vir.shape[0]
+    nmo, naux = nocc + nvir, Bf.shape[2]
+    _need(Bf, (nmo, nmo, naux), "Bf")
+    for t, shp, name in ((P_ij, (nocc, nocc), "P_ij"), (P_ab, (nvir, nvir), "P_ab"), (L1, (nocc, nmo), "L1"),
+                         (L2, (nvir, nmo), "L2"), (eps_occ, (nocc,), "eps_occ"), (eps_vir, (nvir,), "eps_vir")):
+        _need(t, shp, name)
+    D_ai = torch.empty((nvir, nocc), dtype=torch.float64, device=Bf.device)
+    L = _L()
+    ws = _ws(L.rimp2_zvector_workspace_size, nocc, nvir, naux, device=Bf.device)
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    _check(L.rimp2_zvector(nocc, nvir, naux, _ptr(Bf), _ptr(eps_occ), _ptr(eps_vir), _ptr(P_ij), _ptr(P_ab),
+                           _ptr(L1), _ptr(L2), _ptr(D_ai), tol, max_iter, ctypes.byref(it), ctypes.byref(res),
+                           _ptr(ws), ws.numel(), _stream_handle(stream)))
+    return D_ai, it.value, res.value
+
+
+def energy_weighted_density(Bf, eps_occ, eps_vir, P_ij, P_ab, D_ai, L1, L2, stream=None) -> torch.Tensor:
+    """W [nmo][nmo] on the GPU (rimp2_energy_weighted_density)."""
+    nocc, nvir = eps_occ.shape[0], eps_vir.shape[0]
+    nmo, naux = nocc + nvir, Bf.shape[2]
+    _need(Bf, (nmo, nmo, naux), "Bf")
+    W = torch.empty((nmo, nmo), dtype=torch.float64, device=Bf.device)
+    L = _L()
+    ws = _ws(L.rimp2_energy_weighted_density_workspace_size, nocc, nvir, naux, device=Bf.device)
+    _check(L.rimp2_energy_weighted_density(nocc, nvir, naux, _ptr(Bf), _ptr(eps_occ), _ptr(eps_vir), _ptr(P_ij),
+                                           _ptr(P_ab), _ptr(D_ai), _ptr(L1), _ptr(L2), _ptr(W), _ptr(ws), ws.numel(),
+                                           _stream_handle(stream)))
+    return W

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librimp2.so")
 
 RIMP2_OK, RIMP2_EINVAL, RIMP2_ENOMEM, RIMP2_EWORKSPACE = 0, -1, -2, -3
-RIMP2_EDEVICE, RIMP2_EGAP, RIMP2_ENOTSUP = -4, -5, -6
+RIMP2_EDEVICE, RIMP2_EGAP, RIMP2_ENOTSUP, RIMP2_ENOCONV = -4, -5, -6, -7
 FP64, SPLIT_INT8 = 0, 1
 WANT_GAMMA, WANT_DENSITY = 1, 2
 
@@ -109,7 +109,7 @@ def lib():
 
 def _status_name(code: int) -> str:
     names = {0: "RIMP2_OK", -1: "RIMP2_EINVAL", -2: "RIMP2_ENOMEM", -3: "RIMP2_EWORKSPACE", -4: "RIMP2_EDEVICE",
-             -5: "RIMP2_EGAP", -6: "RIMP2_ENOTSUP"}
+             -5: "RIMP2_EGAP", -6: "RIMP2_ENOTSUP", -7: "RIMP2_ENOCONV"}
     return names.get(code, "unknown")
 
 

@@ -145,3 +145,24 @@ def test_gamma_ao_and_l_terms_host_errors():
     assert b"L1 needs I_qa" in L.rimp2_last_error()
     assert L.rimp2_l_terms(2, 3, 5, 8, 256, 512, 768, 1024, 2048, 4096, 16, None) == rm.RIMP2_ENOMEM
     assert L.rimp2_l_terms(0, 3, 5, 8, 256, 512, 768, 1024, 2048, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
+
+
+def test_response_host_errors():
+    import ctypes as C
+    from paper_2410_21888_amd import gradient as G
+    L = G._L()
+    n = C.c_size_t(0)
+    assert L.rimp2_antisym_workspace_size(5, 4, 2, 3, C.byref(n)) == rm.RIMP2_OK and n.value > 0
+    # rows past nmo, ldf too small
+    assert L.rimp2_antisym_term(5, 4, 4, 2, 0, 3, 256, 512, 1024, 3, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_antisym_term(5, 4, 0, 2, 0, 3, 256, 512, 1024, 2, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
+    assert L.rimp2_antisym_term(5, 4, 0, 2, 0, 3, 256, 512, 1024, 3, 4096, 8, None) == rm.RIMP2_ENOMEM
+    it, res = C.c_int32(0), C.c_double(0.0)
+    args = [256, 512, 768, 1024, 1280, 1536, 1792, 2048]
+    assert L.rimp2_zvector(2, 3, 4, *args, 0.0, 10, C.byref(it), C.byref(res), 4096, 1 << 30,
+                           None) == rm.RIMP2_EINVAL          # tol must be positive
+    assert L.rimp2_zvector(2, 3, 4, *args, 1e-10, 0, C.byref(it), C.byref(res), 4096, 1 << 30,
+                           None) == rm.RIMP2_EINVAL          # max_iter >= 1
+    assert L.rimp2_zvector(2, 3, 4, *args, 1e-10, 10, None, None, 4096, 16, None) == rm.RIMP2_ENOMEM
+    assert R.lib().rimp2_status_string(-7) == b"RIMP2_ENOCONV"
+    assert L.rimp2_energy_weighted_density(0, 3, 4, *args, 2304, 4096, 1 << 30, None) == rm.RIMP2_EINVAL
