@@ -150,7 +150,9 @@ def main():
                          "generated on the GPU before it runs (for sets that do not fit in HBM); times the "
                          "batches only")
     ap.add_argument("--steps", type=int, default=3, help="timed steps requested (large: capped by --budget-s)")
-    ap.add_argument("--warmup", type=int, default=1, help="warmup steps requested (large: at least one runs)")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="warmup steps requested (large: at least one runs, unless 0 is asked for, as profiler runs "
+                         "do: then the first step is timed, one step only)")
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="large: wall-clock budget of the whole run from process start; the timed step count "
                          "is cut to what fits after the first warmup step")
@@ -236,22 +238,29 @@ def bench_large(args, torch, synth, rm, dev):
     def step_eg():
         rm.fragment_into(B, deo, dev_, E, G, None, None, ep, workspace=ws, opts=opts)
 
-    # the first step is always a warmup step (the paper discards its first time step)
-    t0 = time.perf_counter()
-    step()
-    torch.cuda.synchronize()
-    step_s = time.perf_counter() - t0
-    log("warmup step 0: %.2f s" % step_s)
-    if rm.read_status(ws) != rm.RIMP2_OK:
-        raise SystemExit("device status not OK (orbital-energy gap)")
+    # the first step is a warmup step (the paper discards its first time
+    # step), unless --warmup 0 asks for a single timed step (profiler runs)
+    cold = args.warmup == 0
+    step_s = 0.0
+    if not cold:
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        step_s = time.perf_counter() - t0
+        log("warmup step 0: %.2f s" % step_s)
+        if rm.read_status(ws) != rm.RIMP2_OK:
+            raise SystemExit("device status not OK (orbital-energy gap)")
     # work kept for after the timed steps: the E+Gamma sub-record (up to two
     # steps of at most a full step each), the CPU baseline and the copies
     cpu_est = 0.0 if args.no_cpu_baseline else 20.0 + 3.0e-12 * rm.flops(nocc, nvir, naux)["algorithmic"] / nocc
     reserve = (0.0 if args.no_e_gamma else 2.0 * step_s) + cpu_est + 15.0
     if args.compare_fp64:
         reserve += 1.2 * step_s
-    warmup, steps = plan_steps(args.steps, args.warmup, args.budget_s, time.perf_counter() - T_START, step_s,
-                               reserve)
+    if cold:
+        warmup, steps = 0, 1
+    else:
+        warmup, steps = plan_steps(args.steps, args.warmup, args.budget_s, time.perf_counter() - T_START, step_s,
+                                   reserve)
     log("plan: %d timed step(s), %d warmup step(s) (requested %d and %d, budget %.0f s, reserve %.0f s)"
         % (steps, warmup, args.steps, args.warmup, args.budget_s, reserve))
     for w in range(1, warmup):
@@ -269,6 +278,10 @@ def bench_large(args, torch, synth, rm, dev):
     stats = rm.timing_collect()
     rm.timing_enable(False)
     log("timed %d step(s) in %.3f s" % (steps, t1 - t0))
+    if cold:
+        step_s = t1 - t0
+        if rm.read_status(ws) != rm.RIMP2_OK:
+            raise SystemExit("device status not OK (orbital-energy gap)")
     E_full = E.cpu().numpy().copy()
     ep0_full = ep[0].cpu().numpy().copy()
     G0_full = G[0].cpu().numpy().copy()
@@ -365,11 +378,16 @@ def bench_large(args, torch, synth, rm, dev):
     if not args.no_e_gamma and left() > step_s + cpu_est:
         fl_eg = rm.flops(nocc, nvir, naux, gamma=True, density=False)
         eg_warm = 0
+        if cold:
+            rm.timing_enable(True)
         t2 = time.perf_counter()
         step_eg()
         torch.cuda.synchronize()
         eg_first = time.perf_counter() - t2
-        if left() > eg_first * 1.05 + cpu_est:
+        st_first = rm.timing_collect() if cold else []
+        if cold:
+            rm.timing_enable(False)
+        if not cold and left() > eg_first * 1.05 + cpu_est:
             eg_warm = 1
             rm.timing_enable(True)
             t2 = time.perf_counter()
@@ -379,7 +397,7 @@ def bench_large(args, torch, synth, rm, dev):
             st_eg = rm.timing_collect()
             rm.timing_enable(False)
         else:
-            eg_s, st_eg = eg_first, []
+            eg_s, st_eg = eg_first, st_first
         E_eg = E.cpu().numpy().copy()
         eg = {"value": round(fl_eg["algorithmic"] / eg_s / 1e12, 4), "unit": "TFLOP/s",
               "ms_per_step": round(eg_s * 1e3, 3), "steps": 1, "warmup": eg_warm,
