@@ -485,6 +485,24 @@ def bench_mbe3(args, torch, synth, rm, dev):
     if int(status.abs().sum()) != 0:
         raise SystemExit("device status not OK")
     E_batch = torch.stack([d["E"] for d in frags]).clone()
+    # sampled parity in the timed launch configuration: the smallest, a middle
+    # and the largest fragment of at most 40 occupied orbitals, against the
+    # CPU oracle on the device's own B (read back)
+    sampled = []
+    if not args.no_cpu_baseline:
+        from oracle import rimp2_oracle as O
+        cand = sorted((i for i in range(len(frags)) if frags[i]["B"].shape[0] <= 40),
+                      key=lambda i: frags[i]["B"].shape[0])
+        for i in sorted({cand[0], cand[len(cand) // 2], cand[-1]} if cand else set()):
+            d = frags[i]
+            ref = O.fragment(d["B"].cpu().numpy(), d["eps_occ"].cpu().numpy(), d["eps_vir"].cpu().numpy())
+            e = E_batch[i].cpu().numpy()
+            g = d["Gamma"].cpu().numpy()
+            sampled.append({"nocc": int(d["B"].shape[0]),
+                            "abs_dE_Eh": abs(math.fsum([float(e[0]), float(e[1]), -ref["E_hi"], -ref["E_lo"]])),
+                            "gamma_rel_fro": float(np.linalg.norm(g - ref["Gamma"]) / np.linalg.norm(ref["Gamma"])),
+                            "p_ab_rel_fro": float(np.linalg.norm(d["P_ab"].cpu().numpy() - ref["P_ab"]) /
+                                                  np.linalg.norm(ref["P_ab"]))})
     rm.timing_enable(True)
     t_batch = timed(lambda: batch.run(ws, status), args.steps)
     stats = rm.timing_collect()
@@ -594,6 +612,7 @@ def bench_mbe3(args, torch, synth, rm, dev):
                      "shapes": len(rep), "shapes_off_default": n_changed, "E_bitwise_equal_to_fixed": tuned_bitwise,
                      "chosen_tiles": decisions},
         "max_abs_dE_batch_vs_loop_Eh": dE,
+        "sampled_parity": sampled,
         "split": split,
         "roofline": {"bound": "mfma", "kernel": dom["name"] + " (grouped)", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None,
@@ -754,6 +773,22 @@ def bench_screen(args, torch, synth, rm, dev):
     print("[bench] unscreened energy-only run %.3f s" % t0, file=sys.stderr, flush=True)
     ep0 = e_pair.cpu().numpy().copy()
     E0 = E.cpu().numpy().copy()
+    # sampled parity at full size, in the launch configuration timed: e_ij of
+    # 6 pairs (near, middle and far) against the oracle on the device's own B
+    from oracle import rimp2_oracle as O
+    B_np = B.cpu().numpy()
+    eo_np, ev_np = eo.cpu().numpy(), ev.cpu().numpy()
+    dist = np.sqrt(((r[:, None, :] - r[None, :, :]) ** 2).sum(-1))
+    iu_all = np.triu_indices(nocc, 1)
+    order_d = np.argsort(dist[iu_all])
+    picks = [order_d[0], order_d[len(order_d) // 3], order_d[len(order_d) // 2], order_d[2 * len(order_d) // 3],
+             order_d[-1]]
+    pair_checks = [(0, 0)] + [(int(iu_all[0][q]), int(iu_all[1][q])) for q in picks]
+    max_rel_pair = 0.0
+    for (pi_, pj_) in pair_checks:
+        ref_e = float(O.pair_energy(B_np, eo_np, ev_np, pi_, pj_))
+        max_rel_pair = max(max_rel_pair, abs(ep0[pi_, pj_] - ref_e) / abs(ref_e))
+    del B_np
     off = ~np.eye(nocc, dtype=bool)
     ptrue = np.log10(np.maximum(-ep0[iu], 1e-300))
     pp = pred.reshape(nocc, nocc).cpu().numpy()[iu]
@@ -816,6 +851,7 @@ def bench_screen(args, torch, synth, rm, dev):
         "model": {"rmse_log10_eval": rmse, "train_data_s": round(t_data, 1), "train_fit_s": round(t_fit, 1),
                   "saved_to": args.screen_save or None},
         "E_unscreened": [float(E0[0]), float(E0[1])],
+        "sampled_parity": {"pairs": pair_checks, "e_pair_max_rel": max_rel_pair},
         "roofline": {"bound": "mfma", "kernel": "ints_gemm", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None},
     }

@@ -8,7 +8,8 @@ stored; its rows are computed here with oracle.gamma_rows, at every tile edge
 of the virtual index (a = 0, 127, 128, 1799 against 128-wide GEMM tiles) for
 occupied orbitals at the edges of the slab groups of 6 (k = 0, 5, 6) and in
 the last, ragged group (k = 198, 199), plus two interior ones.  Every element
-is held to |d| <= 1e-12 |ref| + 1e-12 max|ref row|.
+is held to |d| <= 1e-12 |ref| + 1e-12 max|ref row|.  The symmetric path (E and
+Gamma without P) runs at full size too and is held to the same bars.
 """
 import math
 import os
@@ -58,12 +59,33 @@ def test_large_fragment_against_stored_oracle():
     assert_elementwise(pab[rows], g["P_ab_rows"], 1e-12, 1e-12, "P_ab rows")
     assert rel_fro(np.diag(pab), g["P_ab_diag"]) <= 1e-12
     assert abs(np.linalg.norm(pab) - float(g["P_ab_fro"])) <= 1e-12 * float(g["P_ab_fro"])
-    del dB
+    # the same at full size through the symmetric path (E and Gamma without P:
+    # each unordered pair once, the transposed blocks through the second GEMM);
+    # rows past the first slab group get their earlier-group contributions
+    # from the transposed GEMM
+    Gam_full = {}
     avals = [0, 127, 128, 900, 1799]
-    for i in (0, 5, 6, 57, 120, 198, 199):
-        got = r.Gamma[i, avals].cpu().numpy()
+    irows = (0, 5, 6, 57, 120, 198, 199)
+    for i in irows:
+        Gam_full[i] = r.Gamma[i, avals].cpu().numpy()
+    del r
+    torch.cuda.empty_cache()
+    say("large golden: running the symmetric path (E and Gamma only)")
+    rs = rm.fragment(dB, deo, dev_, density=False)
+    torch.cuda.synchronize()
+    Es = rs.E.cpu().numpy()
+    dEs = abs(math.fsum([float(Es[0]), float(Es[1]), -float(g["E"][0]), -float(g["E"][1])]))
+    say("large golden: symmetric path |dE| = %.3e Eh" % dEs)
+    assert dEs <= 1e-6
+    eps_ = rs.e_pair.cpu().numpy()
+    assert np.all(np.abs(eps_ - ref_ep) <= 1e-12 * np.abs(ref_ep) + 1e-15)
+    Gam_sym = {i: rs.Gamma[i, avals].cpu().numpy() for i in irows}
+    del rs, dB
+    torch.cuda.empty_cache()
+    for i in irows:
         ref = O.gamma_rows(B, eo, ev, i, avals)
-        err = rel_fro(got, ref)
-        say("large golden: Gamma[%d, %s, :] rel err %.2e" % (i, avals, err))
-        assert err <= 1e-12
-        assert_elementwise(got, ref, 1e-12, 1e-12, "Gamma[%d]" % i)
+        for name, got in (("ordered", Gam_full[i]), ("symmetric", Gam_sym[i])):
+            err = rel_fro(got, ref)
+            say("large golden: %s Gamma[%d, %s, :] rel err %.2e" % (name, i, avals, err))
+            assert err <= 1e-12
+            assert_elementwise(got, ref, 1e-12, 1e-12, "%s Gamma[%d]" % (name, i))
