@@ -39,6 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+INT8_PEAK_TOPS = 5000.0      # dense INT8 MFMA, 5.0 POP/s
 METRIC = "RI-MP2 E+Γ TFLOP/s & %peak; split-prec/batched vs FP64 speedup at |ΔE|≤1µEh"
 
 
@@ -346,7 +347,17 @@ def bench_large(args, torch, synth, rm, dev):
         out["dtype"] = "int8 digit products (Ozaki), f64 elsewhere"
         out["config"]["precision"] = "split-int8 ints=%d gamma=%d digits" % (args.split_slices or 7,
                                                                              args.split_slices_gamma or 5)
-        out["roofline"]["note"] = "FP64-equivalent rate of the split kernel against the FP64 peak"
+        # the split products run on INT8 MFMA: their roofline is the INT8 peak, on the
+        # INT8 operations executed (S(S+1)/2 digit products per FP64-equivalent product)
+        if dom["name"] in ("ints_oz8", "gamma_oz8"):
+            S = (args.split_slices or 7) if dom["name"] == "ints_oz8" else (args.split_slices_gamma or 5)
+            ops = dom["exec_flops"] * S * (S + 1) / 2 / (dom["total_ms"] / 1e3) / 1e12
+            out["roofline"].update({
+                "achieved": round(ops, 2), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": round(ops / INT8_PEAK_TOPS, 4), "digits": S,
+                "fp64_equivalent_tflops": round(executed, 4),
+                "note": "INT8 digit products executed per second against the dense INT8 MFMA peak; "
+                        "fp64_equivalent_tflops is the same launch's FP64-equivalent rate"})
     wd.rec = out
 
     def left():

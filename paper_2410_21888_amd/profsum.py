@@ -102,8 +102,9 @@ def role_of(name: str) -> str:
                       ("relocate_tables", "status_copy"), ("zero_counters", "status_copy"),
                       (COPY_KERNEL, "(runtime copy)"), ("at::native", "(torch)"), ("three_index", "(input generator)")):
         if key in name:
-            if role is None:
-                return "oz8"
+            if role is None:   # the split-precision products, by digit count
+                m2 = re.search(r"gemm_oz8_kernel<\s*(\d+)", name)
+                return "oz8 S=%s" % m2.group(1) if m2 else "oz8"
             return role
     return "(other)"
 
@@ -155,7 +156,27 @@ def _per_kernel(counter_csv: str, counter: str):
     return d
 
 
-def traffic(fetch_csv: str, write_csv: str):
+def _split_roles(vals: dict, first: dict) -> dict:
+    """Per dispatch (in dispatch order) the role, with the launches of a role
+    past the first first[role] ones named "<role> (later)"."""
+    seen = defaultdict(int)
+    out = {}
+    for key in sorted(vals, key=lambda k: int(k)):
+        name, _ = vals[key]
+        role = role_of(name)
+        if role in first:
+            seen[role] += 1
+            if seen[role] > first[role]:
+                role = role + " (later)"
+        out[key] = role
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, first: dict | None = None):
+    """Calibrated HBM bytes per launch and role.  ``first`` = {role: N} keeps
+    the first N launches of a role under its name and the rest as
+    "<role> (later)" (two runs of the same kernel in one process)."""
+    first = first or {}
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
     # calibration: the largest runtime copy of each run moved CALIB_BYTES each way
@@ -165,15 +186,16 @@ def traffic(fetch_csv: str, write_csv: str):
         raise SystemExit("no calibration copy found (run bench.py with --calib-copy)")
     fs, ws = CALIB_BYTES / (f_copy * 1024.0), CALIB_BYTES / (w_copy * 1024.0)
     acc = defaultdict(lambda: [0, 0.0, 0.0])
+    n_f = defaultdict(int)
     for vals, idx in ((fetch, 1), (write, 2)):
-        for name, v in vals.values():
-            role = role_of(name)
+        roles = _split_roles(vals, first)
+        for key, (name, v) in vals.items():
+            role = roles[key]
             if role.startswith("("):
                 continue
             acc[role][idx] += v
-    n_f = defaultdict(int)
-    for name, _ in fetch.values():
-        n_f[role_of(name)] += 1
+            if idx == 1:
+                n_f[role] += 1
     out = {}
     for role, (_, f_kib, w_kib) in acc.items():
         n = n_f[role] or 1
@@ -200,10 +222,12 @@ def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
         simds, xccs = _agent(counter_csv)
     busy = _per_kernel(counter_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
     gui = _per_kernel(counter_csv, "GRBM_GUI_ACTIVE")
+    lds = _per_kernel(counter_csv, "SQ_LDS_IDX_ACTIVE")
+    conf = _per_kernel(counter_csv, "SQ_LDS_BANK_CONFLICT")
     dur = {}
     for r in _rows(counter_csv):
         dur[r["Dispatch_Id"]] = _num(r["End_Timestamp"]) - _num(r["Start_Timestamp"])
-    acc = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    acc = defaultdict(lambda: [0, 0.0, 0.0, 0.0, 0.0, 0.0])
     for key, (name, b) in busy.items():
         role = role_of(name)
         if role.startswith("(") or key not in gui:
@@ -213,10 +237,16 @@ def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
         e[1] += dur.get(key, 0.0)
         e[2] += b
         e[3] += gui[key][1] / xccs
+        e[4] += lds[key][1] if key in lds else 0.0
+        e[5] += conf[key][1] if key in conf else 0.0
     out = {}
-    for role, (n, ns, b, cyc) in acc.items():
+    cus = simds // 4
+    for role, (n, ns, b, cyc, li, lc) in acc.items():
         out[role] = {"launches": n, "avg_ms": ns / n / 1e6, "clock_ghz": cyc / ns if ns > 0 else 0.0,
                      "mfma_busy": b / (cyc * simds) if cyc > 0 else 0.0}
+        if lds:   # LDS busy with indexed accesses, per CU, and the bank-conflict share of those cycles
+            out[role]["lds_util"] = li / (cyc * cus) if cyc > 0 else 0.0
+            out[role]["lds_conflict"] = lc / li if li > 0 else 0.0
     return out
 
 
@@ -230,22 +260,31 @@ def main(argv=None):
     h.add_argument("write_csv")
     h.add_argument("--workload", required=True)
     h.add_argument("--json", help="merge the result into this JSON file")
+    h.add_argument("--first", action="append", default=[], metavar="ROLE=N",
+                   help="keep the first N launches of ROLE under its name, the rest as 'ROLE (later)'")
     m = sub.add_parser("mfma")
     m.add_argument("counter_csv")
     a = ap.parse_args(argv)
     if a.cmd == "mfma":
         print("Kernel sources hash: %s\n" % kernel_source_hash())
-        print("| role | launches | average ms | clock GHz | matrix units busy |")
-        print("|---|---|---|---|---|")
-        for role, e in sorted(mfma(a.counter_csv).items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"]):
-            print("| %s | %d | %.3f | %.2f | %.1f%% |" % (role, e["launches"], e["avg_ms"], e["clock_ghz"],
-                                                         100.0 * e["mfma_busy"]))
+        res = mfma(a.counter_csv)
+        with_lds = any("lds_util" in e for e in res.values())
+        print("| role | launches | average ms | clock GHz | matrix units busy |" + (" LDS busy | LDS bank-conflict cycles |"
+                                                                             if with_lds else ""))
+        print("|---|---|---|---|---|" + ("---|---|" if with_lds else ""))
+        for role, e in sorted(res.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"]):
+            line = "| %s | %d | %.3f | %.2f | %.1f%% |" % (role, e["launches"], e["avg_ms"], e["clock_ghz"],
+                                                         100.0 * e["mfma_busy"])
+            if with_lds:
+                line += " %.1f%% | %.1f%% |" % (100.0 * e.get("lds_util", 0.0), 100.0 * e.get("lds_conflict", 0.0))
+            print(line)
         return 0
     if a.cmd == "trace":
         print("Kernel sources hash: %s\n" % kernel_source_hash())
         print(trace_summary(a.stats_csv))
         return 0
-    roles, cal = traffic(a.fetch_csv, a.write_csv)
+    first = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in a.first}
+    roles, cal = traffic(a.fetch_csv, a.write_csv, first)
     src = kernel_source_hash()
     print("Calibration: FETCH_SIZE x%.4f, WRITE_SIZE x%.4f (copy read %.0f / %.0f KiB for 1 GiB)\n" % (
         cal["fetch_scale"], cal["write_scale"], cal["fetch_copy_kib"], cal["write_copy_kib"]))
