@@ -580,9 +580,14 @@ void launch_split_cols(const double* X, int64_t K, int64_t N, int64_t ld, const 
                      N, ld, cmax, D, kp, e, status);
 }
 template <int S>
-void launch_oz8(OzParams op, hipStream_t st) {
+void launch_oz8(OzParams op, bool windowed, hipStream_t st) {
   const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
-  hipLaunchKernelGGL((gemm_oz8_kernel<S, (S >= 6) ? 1 : 2>), dim3((unsigned)nwg), dim3(256), 0, st, op);
+  // one LDS stage (two workgroups per CU) unless a windowed product with at
+  // most 5 digits, where the double-buffered stage (still two per CU) was faster
+  if (windowed && S <= 5)
+    hipLaunchKernelGGL((gemm_oz8_kernel<S, 2>), dim3((unsigned)nwg), dim3(256), 0, st, op);
+  else
+    hipLaunchKernelGGL((gemm_oz8_kernel<S, 1>), dim3((unsigned)nwg), dim3(256), 0, st, op);
 }
 #define RIMP2_SWITCH_S(S, CALL)                                   \
   switch (S) {                                                    \
@@ -598,6 +603,14 @@ __global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
   if (i < n) p[i] = 0ull;
 }
 
+// A reduction longer than kOzWindowMax runs in windows of kOzWindow, one
+// launch each in stream order, every later window adding into C.  The tiles of
+// one launch then stream digit panels short enough for the caches they share:
+// over the whole 360000-long reduction of the Gamma product the launch fetched
+// more than its staging bytes from beyond the L2, and the windows made the
+// product about 1.5x faster.
+constexpr int64_t kOzWindow = 5632, kOzWindowMax = 8192;
+
 // C[m, n] (m < M, n < N) from split digits; A rows start at a_row0.
 int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32_t* ea, const int8_t* B,
             int64_t b_slice, const int32_t* eb, int64_t M, int64_t N, int64_t kp, double* C, int64_t ldc,
@@ -612,7 +625,18 @@ int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32
   const int64_t nwg = (int64_t)op.tiles_m * op.tiles_n;
   if (int rc = check_grid(nwg, "split GEMM")) return rc;
   const double ef = 2.0 * (double)M * N * kp;
-  return traced(role, af, ef, ab, st, [&] { RIMP2_SWITCH_S(S, launch_oz8<SS>(op, st)); });
+  const bool windowed = kp > kOzWindowMax;
+  const int64_t kc = windowed ? kOzWindow : kp;
+  for (int64_t k0 = 0;; k0 += kc) {
+    op.k0 = k0;
+    op.kc = std::min(kc, kp - k0);
+    op.accumulate = k0 > 0;
+    const double fr = kp > 0 ? (double)op.kc / (double)kp : 1.0;
+    if (int rc = traced(role, af * fr, ef * fr, ab * fr, st,
+                        [&] { RIMP2_SWITCH_S(S, launch_oz8<SS>(op, windowed, st)); }))
+      return rc;
+    if (k0 + kc >= kp) return RIMP2_OK;
+  }
 }
 
 KOperand kop(const double* base, int64_t rs, int64_t kdiv, int64_t ks1) { return KOperand{base, rs, kdiv, ks1}; }
@@ -918,11 +942,20 @@ struct Wave {
   uint64_t sig = 0;             // hash of the wave's fragment sizes (autotuner key)
   int namp, nred_ab, nred_ij;
   int64_t amp_blocks, red_blocks_ab, red_blocks_ij;
+  // split products (precision RIMP2_SPLIT_INT8): grouped (ia|jb) and Gamma
+  // product lists, run in reduction windows (win_* launches each), with one
+  // work counter per launch; the digit splits run per fragment
+  size_t o_oz[2] = {0, 0}, o_oz_pre[2] = {0, 0}, o_cnt_oz = 0;
+  int n_oz[2] = {0, 0};
+  int64_t items_oz[2] = {0, 0};
+  int win_oz[2] = {0, 0};
+  std::vector<size_t> base;     // workspace offset of each fragment's partition
 };
 }  // namespace
 
 struct rimp2_batch_s {
   bool autotune = false;
+  bool split = false;              // grouped split-precision products
   std::vector<rimp2_frag_desc> d;
   std::vector<int32_t> solo;       // fragments run alone
   std::vector<Plan> plan;          // per fragment (solo: own plan; grouped: full-slab plan)
@@ -980,8 +1013,8 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
   if (opts && opts->precision != RIMP2_FP64 && opts->precision != RIMP2_SPLIT_INT8)
     return fail(RIMP2_ENOTSUP, "precision %d is not supported", opts->precision);
   if (opts && opts->pair_skip) return fail(RIMP2_ENOTSUP, "pair_skip is not supported for batches");
-  // split products have no grouped kernels: every fragment then runs alone
-  const bool all_solo = opts && opts->precision == RIMP2_SPLIT_INT8;
+  const bool split = opts && opts->precision == RIMP2_SPLIT_INT8;
+  B->split = split;
   B->d.assign(d, d + nfrag);
   B->autotune = opts && opts->autotune;
   if (opts && (opts->gemm_loader < 0 || opts->gemm_loader > 1))
@@ -998,11 +1031,16 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     if ((rc = want_of(d[f].Gamma, d[f].P_ij, d[f].P_ab, &want))) return fail(rc, "fragment %d: %s", f, g_err);
     rimp2_opts o{};
     o.slab_group = d[f].nocc;     // whole slab
+    if (split) {
+      o.precision = RIMP2_SPLIT_INT8;
+      o.split_slices = opts->split_slices;
+      o.split_slices_gamma = opts->split_slices_gamma;
+    }
     Plan P;
     if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, &o, &P, true)))
       return fail(rc, "fragment %d: %s", f, g_err);
     P.s_gam = 1;
-    if (all_solo || P.total > budget) {
+    if (P.total > budget) {
       solo[f] = 1;
       if ((rc = make_plan(d[f].nocc, d[f].nvir, d[f].naux, want & 1, want & 2, opts, &P)))
         return fail(rc, "fragment %d: %s", f, g_err);
@@ -1043,6 +1081,19 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       W.o_pre[r] = place(t, sizeof(int64_t) * (n + 1));
     }
     W.o_cnt = place(t, kGLists * sizeof(unsigned long long));
+    if (split) {
+      for (int r = 0; r < 2; ++r) {
+        W.o_oz[r] = place(t, sizeof(OzParams) * n);
+        W.o_oz_pre[r] = place(t, sizeof(int64_t) * (n + 1));
+      }
+      // windows of every fragment in the wave (at most this many launches per product)
+      for (int32_t f : W.frags) {
+        const Plan& P = B->plan[f];
+        W.win_oz[0] = std::max<int>(W.win_oz[0], (int)cdiv(P.kpv, kOzWindow));
+        if (P.gamma) W.win_oz[1] = std::max<int>(W.win_oz[1], (int)cdiv(P.kpg, kOzWindow));
+      }
+      W.o_cnt_oz = place(t, sizeof(unsigned long long) * (W.win_oz[0] + W.win_oz[1]));
+    }
     W.tab_bytes = t;
     W.host_off = tab;
     tab = align_up(tab + t);
@@ -1059,6 +1110,9 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     std::vector<int64_t> red_pre(1, 0);
     GemmList gl[kGLists];
     for (auto& l : gl) l.prefix.assign(1, 0);
+    std::vector<OzParams> oz[2];
+    std::vector<int64_t> oz_pre[2] = {{0}, {0}};
+    W.base.assign(n, 0);
     // every GEMM goes to the lists of both candidate tiles of its role
     auto add = [&](int rho, const GemmParams& g0, bool vec) {
       for (int c = 0; c < 2; ++c) {
@@ -1076,6 +1130,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       const rimp2_frag_desc& q = d[f];
       const Plan& P = B->plan[f];
       const size_t base = poff;
+      W.base[i] = base;
       poff = align_up(poff + P.total);
       const int64_t nocc = q.nocc, nvir = q.nvir, naux = q.naux, L = nocc * nvir;
       for (int64_t w : {nocc, nvir, naux, (int64_t)P.gamma, (int64_t)P.density}) sig = (sig ^ (uint64_t)w) * 1099511628211ull;
@@ -1087,7 +1142,32 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       idx[i] = f;
       amp[i] = AmpDesc{V, T, q.eps_occ, q.eps_vir, ep, status, q.nocc, q.nvir, (P.gamma || P.density) ? 0 : 1};
       amp_pre[i + 1] = amp_pre[i] + nocc * nocc;
-      {  // (ia|jb)
+      if (split) {  // (ia|jb) and Gamma as INT8 digit products of the whole slab
+        OzParams z{};
+        z.M = L; z.N = L; z.kp = P.kpv; z.k0 = 0; z.kc = P.kpv;
+        z.A = relp<int8_t>(base + P.off_dbv); z.a_slice = L * P.kpv; z.a_row0 = 0;
+        z.B = z.A; z.b_slice = z.a_slice;
+        z.ea = relp<int32_t>(base + P.off_ev); z.eb = z.ea;
+        z.C = V; z.ldc = L;
+        z.tiles_m = (int32_t)cdiv(L, 64); z.tiles_n = z.tiles_m; z.group_m = 8;
+        z.pair_nvir = (int32_t)nvir;   // blocks j < k: the amplitude pass mirrors them
+        z.status = status;
+        oz[0].push_back(z);
+        oz_pre[0].push_back(oz_pre[0].back() + (int64_t)z.tiles_m * z.tiles_n);
+        if (P.gamma) {
+          OzParams y{};
+          y.M = L; y.N = naux; y.kp = P.kpg; y.k0 = 0; y.kc = P.kpg;
+          y.A = relp<int8_t>(base + P.off_dt); y.a_slice = L * P.kpg; y.a_row0 = 0;
+          y.B = relp<int8_t>(base + P.off_dbg); y.b_slice = naux * P.kpg;
+          y.ea = relp<int32_t>(base + P.off_et); y.eb = relp<int32_t>(base + P.off_eg);
+          y.C = q.Gamma; y.ldc = naux;
+          y.tiles_m = (int32_t)cdiv(L, 64); y.tiles_n = (int32_t)cdiv(naux, 64); y.group_m = 8;
+          y.status = status;
+          oz[1].push_back(y);
+          oz_pre[1].push_back(oz_pre[1].back() + (int64_t)y.tiles_m * y.tiles_n);
+        }
+      }
+      if (!split) {  // (ia|jb)
         GemmParams gp{};
         gp.M = nocc * nvir; gp.N = L; gp.K = naux; gp.kchunk = naux;
         gp.A = KOperand{q.B, naux, INT64_MAX, 0};
@@ -1096,7 +1176,7 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         gp.skip_nvir = (int32_t)nvir; gp.skip_nocc = (int32_t)nocc; gp.pair_upper = 1;
         add(0, gp, kop_vec_rel(gp.A, gp.K) && kop_vec_rel(gp.Bk, gp.K));
       }
-      if (P.gamma) {
+      if (P.gamma && !split) {
         GemmParams gp{};
         gp.M = nocc * nvir; gp.N = naux; gp.K = L; gp.kchunk = L;
         gp.A = KOperand{T, L, INT64_MAX, 0};
@@ -1147,6 +1227,14 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       put(W.o_g[r], gl[r].p.data(), sizeof(GemmParams) * gl[r].p.size());
       put(W.o_pre[r], gl[r].prefix.data(), sizeof(int64_t) * gl[r].prefix.size());
     }
+    if (split) {
+      for (int r = 0; r < 2; ++r) {
+        W.n_oz[r] = (int)oz[r].size();
+        W.items_oz[r] = oz_pre[r].back();
+        put(W.o_oz[r], oz[r].data(), sizeof(OzParams) * oz[r].size());
+        put(W.o_oz_pre[r], oz_pre[r].data(), sizeof(int64_t) * oz_pre[r].size());
+      }
+    }
   }
   // solo fragments use the workspace after all tables
   B->ws_bytes = std::max(ws, align_up(tab + max_solo));
@@ -1187,6 +1275,29 @@ int launch_group_list(int rho, int c, int loader, const GemmGroup& G, int64_t it
     default: RIMP2_G(32, false, ROLE_PIJ, true, 1, 2);
   }
 #undef RIMP2_G
+}
+
+__global__ void relocate_oz_kernel(char* base, OzParams* z, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    OzParams& p = z[i];
+    reloc_t(p.A, base); reloc_t(p.B, base); reloc_t(p.ea, base); reloc_t(p.eb, base);
+    reloc_t(p.C, base); reloc_t(p.status, base);
+  }
+}
+
+// One grouped split-product launch over reduction window `window` of every
+// problem in G (same NBUF choice as launch_oz8 for a windowed product).
+template <int S>
+int launch_oz8_grouped(const OzGroup& G, int64_t items, int64_t window, int role, hipStream_t st) {
+  if (G.nprob == 0 || items == 0) return RIMP2_OK;
+  const int64_t grid = std::min<int64_t>(items, kSlots);
+  return traced(role, 0, 0, 0, st, [&] {
+    if (S <= 5)
+      hipLaunchKernelGGL((gemm_oz8_grouped<S, 2>), dim3((unsigned)grid), dim3(256), 0, st, G, window, kOzWindow);
+    else
+      hipLaunchKernelGGL((gemm_oz8_grouped<S, 1>), dim3((unsigned)grid), dim3(256), 0, st, G, window, kOzWindow);
+  });
 }
 
 // upload: 0 = tables already in the workspace, 1 = copy them from B->host (pinned) on the stream
@@ -1231,6 +1342,16 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
            hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, (unsigned long long*)at(W.o_cnt),
                               kGLists);
            hipLaunchKernelGGL(gap_check_grouped, dim3((unsigned)n), dim3(256), 0, st, (const FragSmall*)at(W.o_fs));
+           if (B->split) {
+             for (int r = 0; r < 2; ++r)
+               if (W.n_oz[r])
+                 hipLaunchKernelGGL(relocate_oz_kernel, dim3((unsigned)cdiv(W.n_oz[r], 256)), dim3(256), 0, st, ws,
+                                    (OzParams*)at(W.o_oz[r]), W.n_oz[r]);
+             const int nc = W.win_oz[0] + W.win_oz[1];
+             if (nc)
+               hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(nc, 256)), dim3(256), 0, st,
+                                  (unsigned long long*)at(W.o_cnt_oz), (int64_t)nc);
+           }
          })))
       return rc;
     auto grp = [&](int r) {
@@ -1263,13 +1384,57 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
       const TileShape cand[2] = {{kBatchTile[rho][0], kBatchTile[rho][0]}, {kBatchTile[rho][1], kBatchTile[rho][1]}};
       return tuned(key, 2, cand, st, launch);
     };
-    if ((rc = run_role(0))) return rc;
+    // split products: the per-fragment digit splits, then one grouped launch
+    // per reduction window (r = 0: (ia|jb), r = 1: Gamma)
+    auto run_split = [&](int r) -> int {
+      int rc2;
+      for (int i = 0; i < n; ++i) {
+        const int32_t f = W.frags[i];
+        const rimp2_frag_desc& q = B->d[f];
+        const Plan& P = B->plan[f];
+        if (r == 1 && !P.gamma) continue;
+        char* fb = ws + W.base[i];
+        const int32_t* status = (const int32_t*)(fb + P.off_status);
+        const int64_t L = (int64_t)q.nocc * q.nvir, naux = q.naux;
+        if (r == 0) {
+          if ((rc2 = traced(R_SPLIT, 0, 0, 0, st, [&] {
+                 RIMP2_SWITCH_S(P.sv, launch_split_rows<SS>(q.B, L, naux, naux, (int8_t*)(fb + P.off_dbv), P.kpv,
+                                                            (int32_t*)(fb + P.off_ev), status, st));
+               })))
+            return rc2;
+        } else {
+          unsigned long long* cmax = (unsigned long long*)(fb + P.off_cmax);
+          const double* T = (const double*)(fb + P.off_T);
+          if ((rc2 = traced(R_SPLIT, 0, 0, 0, st, [&] {
+                 hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, cmax, naux);
+                 hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(naux, 256), (unsigned)cdiv(L, 1024)), dim3(256),
+                                    0, st, q.B, L, naux, naux, cmax, status);
+                 RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(q.B, L, naux, naux, cmax, (int8_t*)(fb + P.off_dbg), P.kpg,
+                                                            (int32_t*)(fb + P.off_eg), status, st));
+                 RIMP2_SWITCH_S(P.sg, launch_split_rows<SS>(T, L, L, L, (int8_t*)(fb + P.off_dt), P.kpg,
+                                                            (int32_t*)(fb + P.off_et), status, st));
+               })))
+            return rc2;
+        }
+      }
+      if (W.n_oz[r] == 0) return RIMP2_OK;
+      const int S = r == 0 ? B->plan[W.frags[0]].sv : B->plan[W.frags[0]].sg;
+      unsigned long long* cnt = (unsigned long long*)at(W.o_cnt_oz) + (r == 0 ? 0 : W.win_oz[0]);
+      for (int w = 0; w < W.win_oz[r]; ++w) {
+        const OzGroup G{(const OzParams*)at(W.o_oz[r]), (const int64_t*)at(W.o_oz_pre[r]), W.n_oz[r], cnt + w};
+        const int role = r == 0 ? R_INTS8 : R_GAMMA8;
+        RIMP2_SWITCH_S(S, rc2 = launch_oz8_grouped<SS>(G, W.items_oz[r], w, role, st));
+        if (rc2) return rc2;
+      }
+      return RIMP2_OK;
+    };
+    if ((rc = B->split ? run_split(0) : run_role(0))) return rc;
     if ((rc = traced(R_AMP, 0, 0, 0, st, [&] {
            hipLaunchKernelGGL(amplitude_grouped, dim3((unsigned)W.amp_blocks), dim3(256), 0, st,
                               (const AmpDesc*)at(W.o_amp), (const int64_t*)at(W.o_amp_pre), n);
          })))
       return rc;
-    if ((rc = run_role(1)) || (rc = run_role(2)) || (rc = run_role(3))) return rc;
+    if ((rc = B->split ? run_split(1) : run_role(1)) || (rc = run_role(2)) || (rc = run_role(3))) return rc;
     if (W.nred_ab && (rc = traced(R_REDUCE, 0, 0, 0, st, [&] {
                         hipLaunchKernelGGL(reduce_grouped, dim3((unsigned)W.red_blocks_ab), dim3(256), 0, st,
                                            (const ReduceDesc*)at(W.o_red), (const int64_t*)at(W.o_red_pre), W.nred_ab);

@@ -147,16 +147,81 @@ def test_batch_autotune_bitwise_and_decides():
     rm.autotune_reset()
 
 
-def test_batch_split_precision_matches_oracle():
-    frags, refs = make_frags(MBE_LIKE)
-    say("split-precision batch of %d fragments" % len(frags))
-    status = torch.full((len(frags),), 7, dtype=torch.int32, device="cuda:0")
-    rm.fragment_batch(frags, status=status, opts=rm.make_opts(precision=rm.SPLIT_INT8))
-    torch.cuda.synchronize()
-    assert status.cpu().tolist() == [0] * len(frags)
+def check_split(frags, refs):
+    """Split-precision bar: |dE| <= 1 uEh; every element of Gamma, P_ij, P_ab
+    and e_pair within 1e-8 |ref| + 1e-8 max|ref row|, and relative Frobenius
+    error <= 1e-8."""
     for d, ref in zip(frags, refs):
         assert energy_error(d["E"], ref["E_hi"], ref["E_lo"]) <= 1e-6
         for key in ("Gamma", "P_ij", "P_ab", "e_pair"):
             got = d[key].cpu().numpy()
             assert rel_fro(got, ref[key]) <= 1e-8, key
             assert_elementwise(got, ref[key], 1e-8, 1e-8, key)
+
+
+def run_split_batch(frags, **kw):
+    status = torch.full((len(frags),), 7, dtype=torch.int32, device="cuda:0")
+    rm.fragment_batch(frags, status=status, opts=rm.make_opts(precision=rm.SPLIT_INT8, **kw))
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(frags)
+
+
+def test_batch_split_precision_matches_oracle():
+    """One wave: grouped split products of every fragment."""
+    frags, refs = make_frags(MBE_LIKE)
+    say("split-precision batch of %d fragments" % len(frags))
+    run_split_batch(frags)
+    check_split(frags, refs)
+
+
+def test_batch_split_waves_and_solo_match_oracle():
+    """A small wave budget: the largest fragments run alone (their own split
+    plan), the rest in several waves of grouped split products."""
+    frags, refs = make_frags(MBE_LIKE)
+    say("split-precision batch of %d fragments, small wave budget" % len(frags))
+    run_split_batch(frags, slab_budget_bytes=3 << 20)
+    check_split(frags, refs)
+
+
+def test_batch_split_windows_match_oracle():
+    """Reductions longer than one window in a wave: the Gamma product of the
+    first fragment (nocc * nvir = 6000) and the (ia|jb) product of the second
+    (naux = 6000) run in two windows; the other fragments have one, and skip
+    their items in the second launch."""
+    frags, refs = make_frags([(3, 2000, 24), (2, 8, 6000), (5, 25, 90), (2, 10, 36)])
+    say("split-precision batch with windowed products")
+    run_split_batch(frags)
+    check_split(frags, refs)
+
+
+def test_batch_split_graph_capture_replays():
+    frags, refs = make_frags(MBE_LIKE[:5])
+    b = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8))
+    ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    status = torch.zeros(len(frags), dtype=torch.int32, device="cuda:0")
+    b.run(ws, status)
+    torch.cuda.synchronize()
+    check_split(frags, refs)
+    eager = [{k: v.clone() for k, v in d.items() if k not in ("B", "eps_occ", "eps_vir")} for d in frags]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run(ws, status)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run(ws, status)
+    for rep in range(3):
+        for d in frags:
+            for k, v in d.items():
+                if k not in ("B", "eps_occ", "eps_vir"):
+                    v.fill_(float("nan") if v.dtype == torch.float64 else 0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("split graph replay %d" % rep)
+        for d, e in zip(frags, eager):
+            for k, v in e.items():
+                assert torch.equal(d[k], v), (rep, k)
+    b.close()

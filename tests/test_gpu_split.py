@@ -47,6 +47,27 @@ def test_split_ragged(shape):
     check(synth.random_fragment(nocc, nvir, naux, seed=sum(shape) + 3), split_opts(g=2))
 
 
+@pytest.mark.parametrize("sv", [5, 7])
+def test_split_long_reduction_windows(sv):
+    """naux = 70000: the (ia|jb) product's reduction runs in windows, one
+    launch each, every later window adding into the output (13 windows)."""
+    check(synth.random_fragment(2, 8, 70000, seed=41), split_opts(sv=sv))
+
+
+def test_split_gamma_windows():
+    """nocc * nvir = 8400: the Gamma product's reduction runs in two windows
+    (the second, short one adding into the first's output)."""
+    f = synth.random_fragment(2, 4200, 24, seed=43)
+    B, eo, ev = f.arrays()
+    say("split Gamma windows nocc=2 nvir=4200 naux=24")
+    r = rm.fragment(*to_dev(B, eo, ev), density=False, opts=split_opts())
+    ref = O.fragment(B, eo, ev, density=False)
+    assert energy_error(r.E, ref["E_hi"], ref["E_lo"]) <= 1e-6
+    g = r.Gamma.cpu().numpy()
+    assert rel_fro(g, ref["Gamma"]) <= 1e-8
+    assert_elementwise(g, ref["Gamma"], 1e-8, 1e-8, "Gamma")
+
+
 def test_split_error_falls_with_digits():
     f = synth.random_fragment(6, 60, 200, seed=21)
     B, eo, ev = f.arrays()
