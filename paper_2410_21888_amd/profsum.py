@@ -262,6 +262,8 @@ def main(argv=None):
     h.add_argument("--json", help="merge the result into this JSON file")
     h.add_argument("--first", action="append", default=[], metavar="ROLE=N",
                    help="keep the first N launches of ROLE under its name, the rest as 'ROLE (later)'")
+    h.add_argument("--later-workload", default="",
+                   help="with --json: file the 'ROLE (later)' entries under this workload, as ROLE")
     m = sub.add_parser("mfma")
     m.add_argument("counter_csv")
     a = ap.parse_args(argv)
@@ -299,7 +301,13 @@ def main(argv=None):
         if os.path.exists(a.json):
             with open(a.json) as fh:
                 d = json.load(fh)
-        d[a.workload] = {r: dict(e, source_hash=src) for r, e in roles.items()}
+        later = " (later)"
+        if a.later_workload:
+            d[a.workload] = {r: dict(e, source_hash=src) for r, e in roles.items() if not r.endswith(later)}
+            d[a.later_workload] = {r[:-len(later)]: dict(e, source_hash=src) for r, e in roles.items()
+                                   if r.endswith(later)}
+        else:
+            d[a.workload] = {r: dict(e, source_hash=src) for r, e in roles.items()}
         d["calibration"] = cal
         with open(a.json, "w") as f:
             json.dump(d, f, indent=1)
