@@ -206,7 +206,7 @@ typedef struct {
  * counter, largest fragment first).  Larger fragments run alone, as
  * rimp2_fragment does.  With opts->precision = RIMP2_SPLIT_INT8 the (ia|jb)
  * and Gamma products of a wave are grouped split products (one persistent
- * launch per reduction window of 5632 over all fragments of the wave), after
+ * launch per reduction window of 2816 over all fragments of the wave), after
  * per-fragment digit splits; P_ab and P_ij stay FP64.  pair_skip must be
  * NULL.  With opts->autotune the grouped FP64 GEMM
  * launches and the fragments that run alone are tuned in situ (see

@@ -93,18 +93,21 @@ def role_of(name: str) -> str:
         if m.group(2) == "1" and m.group(1) == "false":   # K-contiguous B: the metric contraction of Gamma
             return "gamma_metric"
         return _GEMM_ROLES[m.group(2)]
-    for key, role in (("gemm_oz8_kernel<", None), ("amplitude", "amplitude"),
+    for key, role in (("gemm_oz8_", None), ("amplitude", "amplitude"),
                       ("pair_energy_reduce", "amplitude (pair energy reduce)"),
                       ("splitk_reduce", "splitk_reduce"), ("reduce_grouped", "splitk_reduce"),
                       ("energy_sum", "energy_sum"), ("gap_check", "gap_check"), ("split_rows", "digit_split"),
                       ("split_cols", "digit_split"), ("colmax", "digit_split"), ("zero_u64", "digit_split"),
                       ("copy_status", "status_copy"), ("status_copy", "status_copy"),
-                      ("relocate_tables", "status_copy"), ("zero_counters", "status_copy"),
+                      ("relocate_tables", "status_copy"), ("relocate_oz", "status_copy"),
+                      ("zero_counters", "status_copy"),
                       (COPY_KERNEL, "(runtime copy)"), ("at::native", "(torch)"), ("three_index", "(input generator)")):
         if key in name:
             if role is None:   # the split-precision products, by digit count
-                m2 = re.search(r"gemm_oz8_kernel<\s*(\d+)", name)
-                return "oz8 S=%s" % m2.group(1) if m2 else "oz8"
+                m2 = re.search(r"gemm_oz8_(kernel|grouped)<\s*(\d+)", name)
+                if not m2:
+                    return "oz8"
+                return "oz8 S=%s%s" % (m2.group(2), " (grouped)" if m2.group(1) == "grouped" else "")
             return role
     return "(other)"
 
@@ -214,13 +217,15 @@ def _agent(counter_csv: str):
     raise SystemExit("no GPU agent in %s" % path)
 
 
-def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
+def mfma(counter_csv: str, simds: int = 0, xccs: int = 0, first: dict | None = None):
     """{role: {launches, avg_ms, clock_ghz, mfma_busy}} from one PMC run of
     SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (values summed over
-    dimensions; GRBM_GUI_ACTIVE counts once per XCC)."""
+    dimensions; GRBM_GUI_ACTIVE counts once per XCC).  ``first`` splits
+    repeated roles as in traffic()."""
     if not simds:
         simds, xccs = _agent(counter_csv)
     busy = _per_kernel(counter_csv, "SQ_VALU_MFMA_BUSY_CYCLES")
+    roles = _split_roles(busy, first or {})
     gui = _per_kernel(counter_csv, "GRBM_GUI_ACTIVE")
     lds = _per_kernel(counter_csv, "SQ_LDS_IDX_ACTIVE")
     conf = _per_kernel(counter_csv, "SQ_LDS_BANK_CONFLICT")
@@ -229,7 +234,7 @@ def mfma(counter_csv: str, simds: int = 0, xccs: int = 0):
         dur[r["Dispatch_Id"]] = _num(r["End_Timestamp"]) - _num(r["Start_Timestamp"])
     acc = defaultdict(lambda: [0, 0.0, 0.0, 0.0, 0.0, 0.0])
     for key, (name, b) in busy.items():
-        role = role_of(name)
+        role = roles[key]
         if role.startswith("(") or key not in gui:
             continue
         e = acc[role]
@@ -266,10 +271,12 @@ def main(argv=None):
                    help="with --json: file the 'ROLE (later)' entries under this workload, as ROLE")
     m = sub.add_parser("mfma")
     m.add_argument("counter_csv")
+    m.add_argument("--first", action="append", default=[], metavar="ROLE=N",
+                   help="keep the first N launches of ROLE under its name, the rest as 'ROLE (later)'")
     a = ap.parse_args(argv)
     if a.cmd == "mfma":
         print("Kernel sources hash: %s\n" % kernel_source_hash())
-        res = mfma(a.counter_csv)
+        res = mfma(a.counter_csv, first={kv.split("=")[0]: int(kv.split("=")[1]) for kv in a.first})
         with_lds = any("lds_util" in e for e in res.values())
         print("| role | launches | average ms | clock GHz | matrix units busy |" + (" LDS busy | LDS bank-conflict cycles |"
                                                                              if with_lds else ""))

@@ -186,8 +186,8 @@ def test_batch_split_waves_and_solo_match_oracle():
 def test_batch_split_windows_match_oracle():
     """Reductions longer than one window in a wave: the Gamma product of the
     first fragment (nocc * nvir = 6000) and the (ia|jb) product of the second
-    (naux = 6000) run in two windows; the other fragments have one, and skip
-    their items in the second launch."""
+    (naux = 6000) run in three windows of 2816; the other fragments have one,
+    and skip their items in the later launches."""
     frags, refs = make_frags([(3, 2000, 24), (2, 8, 6000), (5, 25, 90), (2, 10, 36)])
     say("split-precision batch with windowed products")
     run_split_batch(frags)

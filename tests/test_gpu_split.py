@@ -50,13 +50,13 @@ def test_split_ragged(shape):
 @pytest.mark.parametrize("sv", [5, 7])
 def test_split_long_reduction_windows(sv):
     """naux = 70000: the (ia|jb) product's reduction runs in windows, one
-    launch each, every later window adding into the output (13 windows)."""
+    launch each, every later window adding into the output (25 windows of 2816)."""
     check(synth.random_fragment(2, 8, 70000, seed=41), split_opts(sv=sv))
 
 
 def test_split_gamma_windows():
-    """nocc * nvir = 8400: the Gamma product's reduction runs in two windows
-    (the second, short one adding into the first's output)."""
+    """nocc * nvir = 8400 (padded to 8448): the Gamma product's reduction runs
+    in three windows of 2816, the later ones adding into the first's output."""
     f = synth.random_fragment(2, 4200, 24, seed=43)
     B, eo, ev = f.arrays()
     say("split Gamma windows nocc=2 nvir=4200 naux=24")

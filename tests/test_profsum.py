@@ -28,6 +28,8 @@ def test_roles_of_kernel_symbols():
     assert profsum.role_of("void rimp2::gemm_f64_grouped<64, 64, 16, false, 3, true, true>(rimp2::GemmGroup)") == "pij_gemm"
     assert profsum.role_of("rimp2::amplitude_kernel(double*, ...)") == "amplitude"
     assert profsum.role_of("__amd_rocclr_copyBuffer") == "(runtime copy)"
+    assert profsum.role_of("void rimp2::gemm_oz8_kernel<7, 1>(rimp2::OzParams)") == "oz8 S=7"
+    assert profsum.role_of("void rimp2::gemm_oz8_grouped<5, 2>(rimp2::OzGroup, long, long)") == "oz8 S=5 (grouped)"
 
 
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
@@ -47,6 +49,26 @@ def test_traffic_scales_by_the_calibration_copy(tmp_path):
     with open(out) as fh:
         d = json.load(fh)
     assert d["w"]["ints_gemm"]["source_hash"] == profsum.kernel_source_hash()
+
+
+def test_traffic_splits_two_runs_into_two_workloads(tmp_path):
+    """One process runs the same kernels twice (two paths): --first keeps the
+    first launches under the role's name, and --later-workload files the rest
+    under a second workload."""
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    write_counters(f, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 524288.0), (GAMMA, 10.0), (GAMMA, 10.0),
+                                     (GAMMA, 40.0), (INTS, 5.0)])
+    write_counters(w, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 1048576.0), (GAMMA, 1.0), (GAMMA, 1.0),
+                                     (GAMMA, 4.0), (INTS, 1.0)])
+    out = tmp_path / "t.json"
+    assert profsum.main(["traffic", str(f), str(w), "--workload", "a", "--first", "gamma_gemm=2",
+                         "--first", "ints_gemm=0", "--later-workload", "b", "--json", str(out)]) == 0
+    with open(out) as fh:
+        d = json.load(fh)
+    assert set(d["a"]) == {"gamma_gemm"} and set(d["b"]) == {"gamma_gemm", "ints_gemm"}
+    assert d["a"]["gamma_gemm"]["launches"] == 2 and d["b"]["gamma_gemm"]["launches"] == 1
+    assert abs(d["a"]["gamma_gemm"]["bytes_per_launch"] - (10.0 * 2 + 1.0) * 1024) < 1e-6
+    assert abs(d["b"]["gamma_gemm"]["bytes_per_launch"] - (40.0 * 2 + 4.0) * 1024) < 1e-6
 
 
 def test_mfma_occupancy_and_clock(tmp_path):
