@@ -179,9 +179,8 @@ def main():
                     help="after the timed steps run one FP64 step and report the differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--outputs", choices=["eg", "all"], default=None,
-                    help="large: outputs of the timed steps: eg = E, e_ij and Gamma (the metric's pair; FP64 runs "
-                         "them on the symmetric path), all = also P_ij and P_ab; default eg for fp64, all for split "
-                         "(the split products run on the ordered path)")
+                    help="large: outputs of the timed steps: eg = E, e_ij and Gamma (the metric's pair, on the "
+                         "symmetric path; the default), all = also P_ij and P_ab (the whole path, ordered pairs)")
     ap.add_argument("--no-sub", "--no-e-gamma", dest="no_sub", action="store_true",
                     help="large: skip the sub-record (the same fragment in the other --outputs form)")
     ap.add_argument("--autotune", action="store_true",
@@ -192,7 +191,7 @@ def main():
                          "scaling profiler byte counters)")
     args = ap.parse_args()
     if args.outputs is None:
-        args.outputs = "eg" if args.precision == "fp64" else "all"
+        args.outputs = "eg"
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
@@ -344,9 +343,8 @@ def bench_large(args, torch, synth, rm, dev):
                    "nocc": nocc, "nvir": nvir, "naux": naux, "seed": args.seed, "aux_decay": args.decay,
                    "outputs": outputs_main,
                    "flops_counted": "algorithmic E+Gamma" if eg_main else "algorithmic E+Gamma+P_ab+P_ij",
-                   "path": ("symmetric: (ia|jb) over pairs j >= k only" if eg_main and args.precision == "fp64"
-                            else "ordered pairs (P needs every ordered pair's T and X)" if not eg_main
-                            else "ordered pairs (split products)"),
+                   "path": ("symmetric: (ia|jb) over pairs j >= k only" if eg_main
+                            else "ordered pairs (P needs every ordered pair's T and X)"),
                    "slab_group": args.slab_group or "auto", "autotune": bool(args.autotune),
                    "inputs": "B generated on the GPU (seeded counter-based normals), resident in HBM"},
         "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
@@ -375,7 +373,7 @@ def bench_large(args, torch, synth, rm, dev):
                                                                              args.split_slices_gamma or 5)
         # the split products run on INT8 MFMA: their roofline is the INT8 peak, on the
         # INT8 operations executed (S(S+1)/2 digit products per FP64-equivalent product)
-        if dom["name"] in ("ints_oz8", "gamma_oz8"):
+        if dom["name"] in ("ints_oz8", "gamma_oz8", "gamma_t_oz8"):
             S = (args.split_slices or 7) if dom["name"] == "ints_oz8" else (args.split_slices_gamma or 5)
             ops = dom["exec_flops"] * S * (S + 1) / 2 / (dom["total_ms"] / 1e3) / 1e12
             out["roofline"].update({

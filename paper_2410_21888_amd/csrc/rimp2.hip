@@ -54,11 +54,12 @@ namespace {
 
 // ---- kernel timing -------------------------------------------------------
 enum Role { R_GAP, R_INTS, R_AMP, R_GAMMA, R_PAB, R_PIJ, R_REDUCE, R_ESUM, R_STATUS, R_SPLIT, R_INTS8, R_GAMMA8,
-            R_GAMMA_T, R_GAMMA_AO, R_LTERM, R_RESPONSE, R_NROLES };
+            R_GAMMA_T, R_GAMMA_AO, R_LTERM, R_RESPONSE, R_GAMMA_T8, R_NROLES };
 const char* const kRoleName[R_NROLES] = {"gap_check",  "ints_gemm",     "amplitude",  "gamma_gemm",
                                          "pab_gemm",   "pij_gemm",      "splitk_reduce", "energy_sum",
                                          "status_copy", "digit_split", "ints_oz8",   "gamma_oz8",
-                                         "gamma_t_gemm", "gamma_ao_gemm", "l_terms_gemm", "response"};
+                                         "gamma_t_gemm", "gamma_ao_gemm", "l_terms_gemm", "response",
+                                         "gamma_t_oz8"};
 struct TraceRec {
   int role;
   hipEvent_t e0, e1;
@@ -165,6 +166,9 @@ struct Plan {
   int sv, sg;                // digits per operand of (ia|jb) and of Gamma
   int64_t kpv, kpg;          // padded reduction lengths of the split products
   size_t off_dbv, off_ev, off_dbg, off_eg, off_cmax, off_dt, off_et;
+  // symmetric path with split products: digits of the transposed T blocks and
+  // of the group's B rows (the transposed-block product), per group
+  size_t off_dtt, off_ett, off_cmt, off_dbk, off_ebk;
   int64_t g;                 // occupied orbitals per slab group
   int64_t s_ab, s_ij, s_gam; // split-K factors
   size_t off_status, off_V, off_T, off_e, off_pab, off_pij, off_gam, off_epart, total;
@@ -224,7 +228,7 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
   p->kpg = cdiv(nocc * nvir, 64) * 64;
   const bool need_T = gamma || density;
   const double slab_per_k = (need_T ? 2.0 : 1.0) * 8.0 * (double)nocc * nvir * nvir;
-  p->sym = gamma && !density && !p->split && !grouped;
+  p->sym = gamma && !density && !grouped;
   p->g_fixed = o && o->slab_group > 0;
   p->budget = (o && o->slab_budget_bytes) ? (double)o->slab_budget_bytes : 64.0 * (1ull << 30);
   int64_t g;
@@ -276,16 +280,47 @@ int make_plan(int64_t nocc, int64_t nvir, int64_t naux, bool gamma, bool density
     off = align_up(off + 16 * (size_t)most);
   }
   p->off_dbv = p->off_ev = p->off_dbg = p->off_eg = p->off_cmax = p->off_dt = p->off_et = off;
+  p->off_dtt = p->off_ett = p->off_cmt = p->off_dbk = p->off_ebk = off;
   if (p->split) {
     const int64_t L = nocc * nvir;
     p->off_dbv = off; off = align_up(off + (size_t)p->sv * L * p->kpv);
     p->off_ev = off; off = align_up(off + 4 * (size_t)L);
-    if (gamma) {
+    if (gamma && !p->sym) {
       p->off_dbg = off; off = align_up(off + (size_t)p->sg * naux * p->kpg);
       p->off_eg = off; off = align_up(off + 4 * (size_t)naux);
       p->off_cmax = off; off = align_up(off + 8 * (size_t)naux);
       p->off_dt = off; off = align_up(off + (size_t)p->sg * g * nvir * p->kpg);
       p->off_et = off; off = align_up(off + 4 * (size_t)g * nvir);
+    } else if (gamma) {
+      // per group at k0 (gc orbitals, Lc = (nocc - k0) nvir columns): T row
+      // digits [S][gc nvir][pad(Lc)], B column digits of rows >= k0 nvir
+      // [S][naux][pad(Lc)], T column digits of the later columns
+      // [S][(nocc - k0 - gc) nvir][pad(gc nvir)], B column digits of the
+      // group's rows [S][naux][pad(gc nvir)]; sized for the largest group
+      double dt = 0, dbg = 0, dtt = 0, dbk = 0, rows = 0, cols = 0;
+      int64_t grid = 0;   // largest digit-split grid (split_cols: 32 x 32 tiles)
+      for (int64_t k0 = 0; k0 < nocc;) {
+        const int64_t gc = group_at(*p, k0), kc = cdiv((nocc - k0) * nvir, 64) * 64, kg = cdiv(gc * nvir, 64) * 64;
+        grid = std::max({grid, cdiv(kc, 32) * cdiv(naux, 32), cdiv(kg, 32) * cdiv((nocc - k0 - gc) * nvir, 32)});
+        dt = std::max(dt, (double)gc * nvir * kc);
+        dbg = std::max(dbg, (double)naux * kc);
+        dtt = std::max(dtt, (double)(nocc - k0 - gc) * nvir * kg);
+        dbk = std::max(dbk, (double)naux * kg);
+        rows = std::max(rows, (double)gc * nvir);
+        cols = std::max(cols, (double)(nocc - k0 - gc) * nvir);
+        k0 += gc;
+      }
+      p->off_dbg = off; off = align_up(off + (size_t)(p->sg * dbg));
+      p->off_eg = off; off = align_up(off + 4 * (size_t)naux);
+      p->off_cmax = off; off = align_up(off + 8 * (size_t)naux);
+      p->off_dt = off; off = align_up(off + (size_t)(p->sg * dt));
+      p->off_et = off; off = align_up(off + (size_t)(4.0 * rows));
+      p->off_dtt = off; off = align_up(off + (size_t)(p->sg * dtt));
+      p->off_ett = off; off = align_up(off + (size_t)(4.0 * cols));
+      p->off_cmt = off; off = align_up(off + (size_t)(8.0 * cols));
+      p->off_dbk = off; off = align_up(off + (size_t)(p->sg * dbk));
+      p->off_ebk = off; off = align_up(off + 4 * (size_t)naux);
+      if (int rc = check_grid(grid, "digit split")) return rc;
     }
   }
   p->total = off;
@@ -613,9 +648,10 @@ __global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
 constexpr int64_t kOzWindow = 2816, kOzWindowMax = 8192;
 
 // C[m, n] (m < M, n < N) from split digits; A rows start at a_row0.
+// acc0: the first window adds into C too (C already holds a partial sum).
 int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32_t* ea, const int8_t* B,
             int64_t b_slice, const int32_t* eb, int64_t M, int64_t N, int64_t kp, double* C, int64_t ldc,
-            const int32_t* status, int role, double af, double ab, hipStream_t st) {
+            const int32_t* status, int role, double af, double ab, hipStream_t st, int acc0 = 0) {
   OzParams op{};
   op.M = M; op.N = N; op.kp = kp;
   op.A = A; op.a_slice = a_slice; op.a_row0 = a_row0;
@@ -631,7 +667,7 @@ int run_oz8(int S, const int8_t* A, int64_t a_slice, int64_t a_row0, const int32
   for (int64_t k0 = 0;; k0 += kc) {
     op.k0 = k0;
     op.kc = std::min(kc, kp - k0);
-    op.accumulate = k0 > 0;
+    op.accumulate = (k0 > 0 || acc0) ? 1 : 0;
     const double fr = kp > 0 ? (double)op.kc / (double)kp : 1.0;
     if (int rc = traced(role, af * fr, ef * fr, ab * fr, st,
                         [&] { RIMP2_SWITCH_S(S, launch_oz8<SS>(op, windowed, st)); }))
@@ -672,8 +708,9 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
            RIMP2_SWITCH_S(P.sv, launch_split_rows<SS>(B, L, naux, naux, dbv, P.kpv, exv, status, st));
          })))
       return rc;
-    if (P.gamma) {
+    if (P.gamma && !P.sym) {
       // column-scaled, transposed digits of B as the [(j,b)][P] operand of Gamma
+      // (the symmetric path splits the rows each group needs, per group)
       unsigned long long* cmax = (unsigned long long*)(ws + P.off_cmax);
       if ((rc = traced(R_SPLIT, 0, 0, 8.0 * naux, st, [&] {
              hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, cmax, naux);
@@ -752,7 +789,25 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
       const double c = (double)ncols;
       const double af = 2.0 * g * v * x * c * v, ab = slab + 8.0 * c * v * x + 8.0 * (1 + acc) * g * v * x;
       const int64_t splits = cdiv(Lc, cdiv(cdiv(Lc, s_g), kBK) * kBK);
-      if (splits > 1) {
+      if (P.split) {
+        // row product: T rows of the group (reduction over (j >= k0, b)) times
+        // the column digits of B's rows j >= k0
+        const int64_t kc = cdiv(Lc, 64) * 64;
+        unsigned long long* cmax = (unsigned long long*)(ws + P.off_cmax);
+        const double* Bj = B + j0 * nvir * naux;
+        if ((rc = traced(R_SPLIT, 0, 0, slab + 16.0 * c * v * x + (double)P.sg * (g * v + x) * kc, st, [&] {
+               RIMP2_SWITCH_S(P.sg, launch_split_rows<SS>(T, gc * nvir, Lc, Lc, dt, kc, ext, status, st));
+               hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, cmax, naux);
+               hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(naux, 256), (unsigned)cdiv(Lc, 1024)), dim3(256),
+                                  0, st, Bj, Lc, naux, naux, cmax, status);
+               RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(Bj, Lc, naux, naux, cmax, dbg, kc, exg, status, st));
+             })))
+          return rc;
+        if ((rc = run_oz8(P.sg, dt, gc * nvir * kc, 0, ext, dbg, naux * kc, exg, gc * nvir, naux, kc, out, naux,
+                          status, R_GAMMA8, af, (double)P.sg * (g * v + x) * kc + 8.0 * (1 + acc) * g * v * x, st,
+                          acc)))
+          return rc;
+      } else if (splits > 1) {
         double* W = (double*)(ws + P.off_gam);
         gp.C = W; gp.ldc = naux; gp.split_stride = gc * nvir * naux;
         if ((rc = launch_tuned(R_GAMMA, gp, P.autotune, P.general, st, af, ab))) return rc;
@@ -779,7 +834,44 @@ int run_fragment(const Plan& P, const double* B, const double* eo, const double*
         gt.status = status;
         const double r = (double)(ncols - gc);
         const double aft = 2.0 * r * v * x * g * v, abt = 8.0 * g * v * r * v + 8.0 * g * v * x + 8.0 * (1 + acc) * r * v * x;
-        if ((rc = launch_tuned(R_GAMMA_T, gt, P.autotune, P.general, st, aft, abt))) return rc;
+        if (P.split) {
+          // transposed-block product: the T columns (j >= k0 + gc, b) over the
+          // group's rows (kk, a) as column digits [S][rows][pad(gc nvir)], and
+          // the group's B rows as column digits [S][naux][pad(gc nvir)]
+          const int64_t kg = cdiv(gc * nvir, 64) * 64;
+          int8_t* dtt = (int8_t*)(ws + P.off_dtt);
+          int32_t* ett = (int32_t*)(ws + P.off_ett);
+          unsigned long long* cmt = (unsigned long long*)(ws + P.off_cmt);
+          int8_t* dbk = (int8_t*)(ws + P.off_dbk);
+          int32_t* ebk = (int32_t*)(ws + P.off_ebk);
+          unsigned long long* cmax = (unsigned long long*)(ws + P.off_cmax);
+          const double* Tt = T + gc * nvir;
+          const double* Bk = B + k0 * nvir * naux;
+          if ((rc = traced(R_SPLIT, 0, 0, 16.0 * g * v * r * v + 16.0 * g * v * x + (double)P.sg * (r * v + x) * kg, st,
+                           [&] {
+                             hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(rows, 256)), dim3(256), 0, st,
+                                                cmt, rows);
+                             hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(rows, 256),
+                                                                    (unsigned)cdiv(gc * nvir, 1024)),
+                                                dim3(256), 0, st, Tt, gc * nvir, rows, Lc, cmt, status);
+                             RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(Tt, gc * nvir, rows, Lc, cmt, dtt, kg, ett,
+                                                                        status, st));
+                             hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st,
+                                                cmax, naux);
+                             hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(naux, 256),
+                                                                    (unsigned)cdiv(gc * nvir, 1024)),
+                                                dim3(256), 0, st, Bk, gc * nvir, naux, naux, cmax, status);
+                             RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(Bk, gc * nvir, naux, naux, cmax, dbk, kg, ebk,
+                                                                        status, st));
+                           })))
+            return rc;
+          if ((rc = run_oz8(P.sg, dtt, rows * kg, 0, ett, dbk, naux * kg, ebk, rows, naux, kg,
+                            Gam + (k0 + gc) * nvir * naux, naux, status, R_GAMMA_T8, aft,
+                            (double)P.sg * (r * v + x) * kg + 8.0 * (1 + acc) * r * v * x, st, acc)))
+            return rc;
+        } else if ((rc = launch_tuned(R_GAMMA_T, gt, P.autotune, P.general, st, aft, abt))) {
+          return rc;
+        }
       }
     } else if (P.gamma) {
       GemmParams gp{};

@@ -68,6 +68,39 @@ def test_split_gamma_windows():
     assert_elementwise(g, ref["Gamma"], 1e-8, 1e-8, "Gamma")
 
 
+@pytest.mark.parametrize("g", [0, 1, 3])
+def test_split_symmetric_e_gamma(g):
+    """E and Gamma without P take the symmetric path with split products: the
+    (ia|jb) products over pairs j >= k0, the Gamma row-block products and the
+    transposed-block products, group after group (g orbitals per group; 0 =
+    the planner's choice, one group here)."""
+    f = synth.random_fragment(7, 90, 150, seed=51)
+    B, eo, ev = f.arrays()
+    say("split symmetric path nocc=7 nvir=90 naux=150 g=%d" % g)
+    r = rm.fragment(*to_dev(B, eo, ev), density=False, opts=split_opts(g=g))
+    ref = O.fragment(B, eo, ev, density=False)
+    assert energy_error(r.E, ref["E_hi"], ref["E_lo"]) <= 1e-6
+    for key, got in (("Gamma", r.Gamma), ("e_pair", r.e_pair)):
+        got = got.cpu().numpy()
+        assert rel_fro(got, ref[key]) <= 1e-8, key
+        assert_elementwise(got, ref[key], 1e-8, 1e-8, key)
+
+
+def test_split_symmetric_windows():
+    """Symmetric path, one orbital per group: the first group's row-block
+    product reduces over 9000 (windowed, the first window storing), the later
+    groups' row products add onto the transposed blocks already in their rows."""
+    f = synth.random_fragment(3, 3000, 16, seed=53)
+    B, eo, ev = f.arrays()
+    say("split symmetric path nocc=3 nvir=3000 naux=16 g=1")
+    r = rm.fragment(*to_dev(B, eo, ev), density=False, opts=split_opts(g=1))
+    ref = O.fragment(B, eo, ev, density=False)
+    assert energy_error(r.E, ref["E_hi"], ref["E_lo"]) <= 1e-6
+    g = r.Gamma.cpu().numpy()
+    assert rel_fro(g, ref["Gamma"]) <= 1e-8
+    assert_elementwise(g, ref["Gamma"], 1e-8, 1e-8, "Gamma")
+
+
 def test_split_error_falls_with_digits():
     f = synth.random_fragment(6, 60, 200, seed=21)
     B, eo, ev = f.arrays()
