@@ -15,6 +15,9 @@ whole path, on ordered pairs).  Prints one JSON line.
              around each of its launches on its stream, against the FP64
              MFMA peak (78.6 TFLOP/s)
   whole_path / e_gamma_only   the same fragment in the other --outputs form
+  split_e_gamma  (FP64 E+Gamma line) the same E+Gamma step with split-precision
+             INT8 products, its speedup over the FP64 step and its differences
+             from the FP64 result
   cpu_baseline  the CPU oracle on one occupied slab (k = 0) of the same
              workload, i.e. 1/nocc of the job, timed on this host's cores
 
@@ -181,6 +184,8 @@ def main():
     ap.add_argument("--outputs", choices=["eg", "all"], default=None,
                     help="large: outputs of the timed steps: eg = E, e_ij and Gamma (the metric's pair, on the "
                          "symmetric path; the default), all = also P_ij and P_ab (the whole path, ordered pairs)")
+    ap.add_argument("--no-split-sub", action="store_true",
+                    help="large, FP64, E+Gamma: skip the split-precision E+Gamma step after the timed steps")
     ap.add_argument("--no-sub", "--no-e-gamma", dest="no_sub", action="store_true",
                     help="large: skip the sub-record (the same fragment in the other --outputs form)")
     ap.add_argument("--autotune", action="store_true",
@@ -240,11 +245,15 @@ def bench_large(args, torch, synth, rm, dev):
                         precision=rm.SPLIT_INT8 if args.precision == "split" else rm.FP64,
                         split_slices=args.split_slices, split_slices_gamma=args.split_slices_gamma,
                         autotune=args.autotune)
-    # the main record's outputs and the sub-record's (the other form), unless --no-sub
+    # the main record's outputs and the sub-record's (the other form), unless
+    # --no-sub; the FP64 E+Gamma line also times the split-precision E+Gamma step
     need_full = not eg_main or not args.no_sub
     need_eg = eg_main or not args.no_sub
+    split_sub = eg_main and args.precision == "fp64" and not args.no_split_sub
+    opts_split = rm.make_opts(slab_group=args.slab_group, precision=rm.SPLIT_INT8) if split_sub else None
     ws = torch.empty(max(rm.workspace_size(nocc, nvir, naux, True, True, opts) if need_full else 0,
-                         rm.workspace_size(nocc, nvir, naux, True, False, opts) if need_eg else 0),
+                         rm.workspace_size(nocc, nvir, naux, True, False, opts) if need_eg else 0,
+                         rm.workspace_size(nocc, nvir, naux, True, False, opts_split) if split_sub else 0),
                      dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -276,6 +285,8 @@ def bench_large(args, torch, synth, rm, dev):
     sub_s = step_s * (1.45 if eg_main else 0.75)
     cpu_est = 0.0 if args.no_cpu_baseline else 20.0 + 3.0e-12 * fl["algorithmic"] / nocc
     reserve = (0.0 if args.no_sub else 2.0 * sub_s) + cpu_est + 15.0
+    if split_sub:   # a split E+Gamma step takes about 0.66 of the FP64 one
+        reserve += 2.0 * 0.7 * step_s + 10.0
     if args.compare_fp64:
         reserve += 1.2 * step_s
     if cold:
@@ -410,6 +421,42 @@ def bench_large(args, torch, synth, rm, dev):
             out["vs_fp64"].update({"p_ij_rel_fro": rel(Pij_s, Pij), "p_ab_rel_fro": rel(Pab_s, Pab)})
         del G_s, ep_s, Pij_s, Pab_s, E_s
         log("FP64 comparison step: %.2f s" % (t3 - t2))
+
+    # the split-precision E+Gamma step on the same inputs (warm, then timed),
+    # against this run's FP64 E+Gamma result: the split-vs-FP64 speedup of the
+    # metric's own outputs
+    if split_sub and left() > 1.5 * step_s + cpu_est + (sub_s if not args.no_sub else 0.0):
+        G64, ep64 = G.clone(), ep.clone()
+        t_split = []
+        for rep in range(2):
+            rm.timing_enable(rep == 1)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rm.fragment_into(B, deo, dev_, E, G, None, None, ep, workspace=ws, opts=opts_split)
+            torch.cuda.synchronize()
+            t_split.append(time.perf_counter() - t2)
+            st_split = rm.timing_collect() if rep == 1 else None
+            rm.timing_enable(False)
+            if rep == 0 and left() < t_split[0] * 1.05 + cpu_est + (sub_s if not args.no_sub else 0.0):
+                break
+        ts = t_split[-1]
+        E_s = E.cpu().numpy().copy()
+        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        out["split_e_gamma"] = {
+            "value": round(fl["algorithmic"] / ts / 1e12, 4), "unit": "TFLOP/s",
+            "flops_counted": "algorithmic E+Gamma (FP64-equivalent)",
+            "ms_per_step": round(ts * 1e3, 3), "steps": 1, "warmup": len(t_split) - 1,
+            "digits": "ints=7 gamma=5", "dtype": "int8 digit products (Ozaki), f64 elsewhere",
+            "speedup_vs_fp64": round(dt / ts, 4),
+            "abs_dE_vs_fp64_Eh": abs(math.fsum([float(E_s[0]), float(E_s[1]), -float(E_main[0]), -float(E_main[1])])),
+            "gamma_rel_fro_vs_fp64": rel(G, G64), "e_pair_rel_fro_vs_fp64": rel(ep, ep64)}
+        if st_split:
+            out["split_e_gamma"]["kernels"] = {x["name"]: {"launches": x["launches"], "ms": round(x["total_ms"], 2)}
+                                               for x in sorted(st_split, key=lambda x: -x["total_ms"])}
+        G.copy_(G64)
+        ep.copy_(ep64)
+        del G64, ep64
+        log("split E+Gamma step: %.2f s (%.3fx the FP64 step)" % (ts, dt / ts))
 
     # the sub-record: the same fragment in the other form (the whole path when
     # the main record is E+Gamma, E+Gamma alone otherwise), timed the same way
