@@ -134,6 +134,10 @@ int rimp2_workspace_size(int32_t nocc, int32_t nvir, int32_t naux, int32_t want,
  *            rimp2_workspace_size() bytes; its content on entry is ignored
  * With opts->pair_skip set, e_ij of a skipped pair is 0 and the pair adds
  * nothing to E, Gamma or P.
+ * With Gamma and without P, every unordered pair's (ia|jb) block is formed
+ * once (pairs j >= k in each slab group) and Gamma takes each pair's block
+ * for both of its orbitals (T_ji = T_ij^T), in FP64 and in split precision;
+ * with P, the slab groups hold every ordered pair.
  */
 int rimp2_fragment(int32_t nocc, int32_t nvir, int32_t naux,
                    const double* B, const double* eps_occ, const double* eps_vir,

@@ -86,6 +86,22 @@ def test_split_symmetric_e_gamma(g):
         assert_elementwise(got, ref[key], 1e-8, 1e-8, key)
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 17, 33), (2, 129, 65), (5, 70, 130)])
+def test_split_symmetric_ragged(shape):
+    """Ragged sizes on the symmetric split path, one orbital per group."""
+    nocc, nvir, naux = shape
+    f = synth.random_fragment(nocc, nvir, naux, seed=sum(shape) + 7)
+    B, eo, ev = f.arrays()
+    say("split symmetric ragged %s" % (shape,))
+    r = rm.fragment(*to_dev(B, eo, ev), density=False, opts=split_opts(g=1))
+    ref = O.fragment(B, eo, ev, density=False)
+    assert energy_error(r.E, ref["E_hi"], ref["E_lo"]) <= 1e-6
+    for key, got in (("Gamma", r.Gamma), ("e_pair", r.e_pair)):
+        got = got.cpu().numpy()
+        assert rel_fro(got, ref[key]) <= 1e-8, key
+        assert_elementwise(got, ref[key], 1e-8, 1e-8, key)
+
+
 def test_split_symmetric_windows():
     """Symmetric path, one orbital per group: the first group's row-block
     product reduces over 9000 (windowed, the first window storing), the later
