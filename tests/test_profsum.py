@@ -91,6 +91,9 @@ def test_mfma_occupancy_and_clock(tmp_path):
     assert abs(e["avg_ms"] - 1.0) < 1e-12
     assert abs(e["clock_ghz"] - 2.4) < 1e-9
     assert abs(e["mfma_busy"] - 0.9) < 1e-12
+    # with first={role: 0} the launch is filed as "(later)"
+    r2 = profsum.mfma(str(c), first={"ints_gemm": 0})
+    assert set(r2) == {"ints_gemm (later)"} and abs(r2["ints_gemm (later)"]["mfma_busy"] - 0.9) < 1e-12
 
 
 def test_source_hash_ignores_comments_and_spacing():
