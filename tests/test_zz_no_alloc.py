@@ -92,6 +92,24 @@ def test_noalloc_symmetric_gamma_and_energy_only():
             assert_elementwise(got.Gamma.cpu().numpy(), ref.Gamma.cpu().numpy(), 1e-12, 1e-12, "Gamma")
 
 
+def test_noalloc_split_precision_matches_fragment():
+    """Split-precision products through the scratch array, whole path and
+    E+Gamma (symmetric path), bit for bit against rimp2_fragment with the
+    same slab group, on two calls in a row (the second smaller)."""
+    for nocc, nvir, naux, g, seed in [(8, 120, 160, 3, 14), (4, 50, 70, 2, 15)]:
+        f = synth.random_fragment(nocc, nvir, naux, seed=seed)
+        d = to_dev(*f.arrays())
+        opts = R.make_opts(slab_group=g, precision=rm.SPLIT_INT8)
+        for density in (True, False):
+            say("noalloc split nocc=%d nvir=%d naux=%d slab_group=%d density=%s" % (nocc, nvir, naux, g, density))
+            got, st = noalloc(*d, opts=opts, density=density)
+            assert st == rm.RIMP2_OK
+            ref = rm.fragment(*d, density=density, opts=opts)
+            for name, a, b in zip(ref._fields, got, ref):
+                if b is not None:
+                    assert torch.equal(a, b), (name, density)
+
+
 def test_noalloc_limits_and_status():
     L = R.lib()
     fn = _fn()
