@@ -194,6 +194,21 @@ def test_batch_split_windows_match_oracle():
     check_split(frags, refs)
 
 
+def test_batch_split_gap_status_per_fragment():
+    """A gap violation in one fragment of a grouped split wave: its status is
+    RIMP2_EGAP, and the digit splits and split products of the others run."""
+    frags, refs = make_frags(MBE_LIKE[:3])
+    bad = frags[1]
+    ev = bad["eps_vir"].clone()
+    ev[0] = bad["eps_occ"].max() - 1e-3
+    bad["eps_vir"] = ev
+    status = torch.full((3,), 7, dtype=torch.int32, device="cuda:0")
+    rm.fragment_batch(frags, status=status, opts=rm.make_opts(precision=rm.SPLIT_INT8))
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0, rm.RIMP2_EGAP, 0]
+    check_split([frags[0], frags[2]], [refs[0], refs[2]])
+
+
 def test_batch_split_graph_capture_replays():
     frags, refs = make_frags(MBE_LIKE[:5])
     b = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8))
