@@ -640,19 +640,26 @@ def bench_mbe3(args, torch, synth, rm, dev):
     E_loop = torch.stack([d["E"] for d in frags]).clone()
     dE = float((E_loop - E_batch).abs().max())
     split = None
-    if args.precision == "split":   # every fragment alone, split products for (ia|jb) and Gamma
+    if args.precision == "split":   # grouped split products for (ia|jb) and Gamma
         sb = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8))
         ws_s = torch.empty(sb.workspace_bytes, dtype=torch.uint8, device=dev)
         sb.run(ws_s, status)
         torch.cuda.synchronize()
+        rm.timing_enable(True)
         t_split = timed(lambda: sb.run(ws_s, status), args.steps)
+        st_split = rm.timing_collect()
+        rm.timing_enable(False)
         E_s = torch.stack([d["E"] for d in frags])
         dE_s = max(abs(math.fsum([float(a[0]), float(a[1]), -float(b[0]), -float(b[1])]))
                    for a, b in zip(E_s.cpu().numpy(), E_batch.cpu().numpy()))
         sb.close()
         del ws_s
         split = {"split_batch_tflops": round(total_alg / t_split / 1e12, 4),
-                 "speedup_split_vs_fp64_batch": round(t_batch / t_split, 4), "max_abs_dE_vs_fp64_Eh": dE_s}
+                 "speedup_split_vs_fp64_batch": round(t_batch / t_split, 4), "max_abs_dE_vs_fp64_Eh": dE_s,
+                 "kernels": {x["name"]: {"launches": x["launches"], "ms": round(x["total_ms"] / args.steps, 2)}
+                             for x in sorted(st_split, key=lambda x: -x["total_ms"])},
+                 "fp64_kernels": {x["name"]: {"launches": x["launches"], "ms": round(x["total_ms"] / args.steps, 2)}
+                                  for x in sorted(stats, key=lambda x: -x["total_ms"])}}
         print("[bench] split-precision batch %.3f s" % t_split, file=sys.stderr, flush=True)
     # in-situ tile autotuning: the first passes trial the candidates, later passes use the choices
     rm.autotune_reset()
