@@ -211,8 +211,8 @@ typedef struct {
  * rimp2_fragment does.  With opts->precision = RIMP2_SPLIT_INT8 the (ia|jb)
  * and Gamma products of a wave are grouped split products (one persistent
  * launch per reduction window of 2816 over all fragments of the wave), after
- * per-fragment digit splits; P_ab and P_ij stay FP64.  pair_skip must be
- * NULL.  With opts->autotune the grouped FP64 GEMM
+ * grouped digit splits (one launch per split step over the wave); P_ab and
+ * P_ij stay FP64.  pair_skip must be NULL.  With opts->autotune the grouped FP64 GEMM
  * launches and the fragments that run alone are tuned in situ (see
  * rimp2_autotune_report).
  *

@@ -1011,6 +1011,21 @@ int noalloc_plan(int64_t nocc, int64_t nvir, int64_t naux, int want, const rimp2
 }
 
 
+// One digit split of one fragment in a batch wave (split precision): rows of
+// X [N][K] (row stride ld) into D [S][N][kp] with exps e[N] (split_row), or
+// columns of X [K][N] into D [S][N][kp] with column maxima cmax[N]
+// (colmax_block, split_cols_tile).  gx: the op's blocks along its first grid
+// dimension (columns: cdiv(N, 256) for the maxima, cdiv(kp, 32) for the
+// digits, which use one op entry each).
+struct DigitOp {
+  const double* X;
+  int64_t K, N, ld, kp, gx;
+  int8_t* D;
+  int32_t* e;
+  unsigned long long* cmax;
+  const int32_t* status;
+};
+
 // ---- batches -----------------------------------------------------------------
 // Grouped GEMM lists of a wave: 4 roles x 2 candidate tiles x 4 loaders
 // (0: two chunks ahead, 1: the same with runs ending inside chunks, 2: the
@@ -1037,12 +1052,18 @@ struct Wave {
   int64_t amp_blocks, red_blocks_ab, red_blocks_ij;
   // split products (precision RIMP2_SPLIT_INT8): grouped (ia|jb) and Gamma
   // product lists, run in reduction windows (win_* launches each), with one
-  // work counter per launch; the digit splits run per fragment
+  // work counter per launch
   size_t o_oz[2] = {0, 0}, o_oz_pre[2] = {0, 0}, o_cnt_oz = 0;
   int n_oz[2] = {0, 0};
   int64_t items_oz[2] = {0, 0};
   int win_oz[2] = {0, 0};
-  std::vector<size_t> base;     // workspace offset of each fragment's partition
+  // grouped digit splits: lists 0 (B rows), 1 (B columns: zero, maxima), 2 (B
+  // column digits), 3 (T rows); each with its op table and four prefix arrays
+  // (one per mode; only the one its launch uses is read)
+  static constexpr int kDigitLists = 4;
+  size_t o_dop[kDigitLists] = {0, 0, 0, 0}, o_dpre[kDigitLists][4] = {};
+  int n_dop[kDigitLists] = {0, 0, 0, 0};
+  int64_t blocks_dop[kDigitLists][4] = {};
 };
 }  // namespace
 
@@ -1186,6 +1207,10 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         if (P.gamma) W.win_oz[1] = std::max<int>(W.win_oz[1], (int)cdiv(P.kpg, kOzWindow));
       }
       W.o_cnt_oz = place(t, sizeof(unsigned long long) * (W.win_oz[0] + W.win_oz[1]));
+      for (int r = 0; r < Wave::kDigitLists; ++r) {
+        W.o_dop[r] = place(t, sizeof(DigitOp) * n);
+        for (int m = 0; m < 4; ++m) W.o_dpre[r][m] = place(t, sizeof(int64_t) * (n + 1));
+      }
     }
     W.tab_bytes = t;
     W.host_off = tab;
@@ -1205,7 +1230,16 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
     for (auto& l : gl) l.prefix.assign(1, 0);
     std::vector<OzParams> oz[2];
     std::vector<int64_t> oz_pre[2] = {{0}, {0}};
-    W.base.assign(n, 0);
+    std::vector<DigitOp> dop[Wave::kDigitLists];
+    std::vector<int64_t> dpre[Wave::kDigitLists][4];
+    for (auto& l : dpre)
+      for (auto& v : l) v.assign(1, 0);
+    // op f of list r: workgroups per mode
+    auto add_dop = [&](int r, const DigitOp& o, int64_t rows_wgs, int64_t zero_wgs, int64_t max_wgs, int64_t dig_wgs) {
+      dop[r].push_back(o);
+      const int64_t w[4] = {rows_wgs, zero_wgs, max_wgs, dig_wgs};
+      for (int m = 0; m < 4; ++m) dpre[r][m].push_back(dpre[r][m].back() + w[m]);
+    };
     // every GEMM goes to the lists of both candidate tiles of its role
     auto add = [&](int rho, const GemmParams& g0, bool vec) {
       for (int c = 0; c < 2; ++c) {
@@ -1223,7 +1257,6 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
       const rimp2_frag_desc& q = d[f];
       const Plan& P = B->plan[f];
       const size_t base = poff;
-      W.base[i] = base;
       poff = align_up(poff + P.total);
       const int64_t nocc = q.nocc, nvir = q.nvir, naux = q.naux, L = nocc * nvir;
       for (int64_t w : {nocc, nvir, naux, (int64_t)P.gamma, (int64_t)P.density}) sig = (sig ^ (uint64_t)w) * 1099511628211ull;
@@ -1247,6 +1280,9 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         z.status = status;
         oz[0].push_back(z);
         oz_pre[0].push_back(oz_pre[0].back() + (int64_t)z.tiles_m * z.tiles_n);
+        // digits of every B row (both operands of the (ia|jb) products)
+        add_dop(0, DigitOp{q.B, naux, L, naux, P.kpv, 0, relp<int8_t>(base + P.off_dbv),
+                           relp<int32_t>(base + P.off_ev), nullptr, status}, L, 0, 0, 0);
         if (P.gamma) {
           OzParams y{};
           y.M = L; y.N = naux; y.kp = P.kpg; y.k0 = 0; y.kc = P.kpg;
@@ -1258,6 +1294,15 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
           y.status = status;
           oz[1].push_back(y);
           oz_pre[1].push_back(oz_pre[1].back() + (int64_t)y.tiles_m * y.tiles_n);
+          // column digits of B (maxima first) and row digits of the T slab
+          unsigned long long* cm = relp<unsigned long long>(base + P.off_cmax);
+          const int64_t gxm = cdiv(naux, 256), gxd = cdiv(P.kpg, 32);
+          add_dop(1, DigitOp{q.B, L, naux, naux, P.kpg, gxm, nullptr, nullptr, cm, status}, 0, gxm,
+                  gxm * cdiv(L, 1024), 0);
+          add_dop(2, DigitOp{q.B, L, naux, naux, P.kpg, gxd, relp<int8_t>(base + P.off_dbg),
+                             relp<int32_t>(base + P.off_eg), cm, status}, 0, 0, 0, gxd * cdiv(naux, 32));
+          add_dop(3, DigitOp{relp<double>(base + P.off_T), L, L, L, P.kpg, 0, relp<int8_t>(base + P.off_dt),
+                             relp<int32_t>(base + P.off_et), nullptr, status}, L, 0, 0, 0);
         }
       }
       if (!split) {  // (ia|jb)
@@ -1327,6 +1372,14 @@ int batch_plan(int32_t nfrag, const rimp2_frag_desc* d, const rimp2_opts* opts, 
         put(W.o_oz[r], oz[r].data(), sizeof(OzParams) * oz[r].size());
         put(W.o_oz_pre[r], oz_pre[r].data(), sizeof(int64_t) * oz_pre[r].size());
       }
+      for (int r = 0; r < Wave::kDigitLists; ++r) {
+        W.n_dop[r] = (int)dop[r].size();
+        put(W.o_dop[r], dop[r].data(), sizeof(DigitOp) * dop[r].size());
+        for (int m = 0; m < 4; ++m) {
+          W.blocks_dop[r][m] = dpre[r][m].back();
+          put(W.o_dpre[r][m], dpre[r][m].data(), sizeof(int64_t) * dpre[r][m].size());
+        }
+      }
     }
   }
   // solo fragments use the workspace after all tables
@@ -1368,6 +1421,44 @@ int launch_group_list(int rho, int c, int loader, const GemmGroup& G, int64_t it
     default: RIMP2_G(32, false, ROLE_PIJ, true, 1, 2);
   }
 #undef RIMP2_G
+}
+
+__device__ __forceinline__ int digit_op_at(const int64_t* prefix, int n, int64_t t) {
+  int lo = 0, hi = n - 1;   // last f with prefix[f] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Grouped digit splits: one launch over every op of a list (prefix counts
+// each op's workgroups).  mode 0: rows; 1: zero cmax; 2: column maxima;
+// 3: column digits.
+template <int S, int MODE>
+__global__ __launch_bounds__(256) void digit_split_grouped(const DigitOp* ops, const int64_t* prefix, int n) {
+  const int f = digit_op_at(prefix, n, blockIdx.x);
+  const DigitOp o = ops[f];
+  if (o.status != nullptr && *o.status != 0) return;
+  const int64_t u = (int64_t)blockIdx.x - prefix[f];
+  if constexpr (MODE == 0) {
+    split_row<S>(o.X, o.N, o.K, o.ld, o.D, o.kp, o.e, u);
+  } else if constexpr (MODE == 1) {
+    const int64_t i = u * 256 + threadIdx.x;
+    if (i < o.N) o.cmax[i] = 0ull;
+  } else if constexpr (MODE == 2) {
+    colmax_block(o.X, o.K, o.N, o.ld, o.cmax, u % o.gx, u / o.gx);
+  } else {
+    split_cols_tile<S>(o.X, o.K, o.N, o.ld, o.cmax, o.D, o.kp, o.e, u % o.gx, u / o.gx);
+  }
+}
+
+__global__ void relocate_digit_kernel(char* base, DigitOp* ops, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    DigitOp& o = ops[i];
+    reloc_t(o.X, base); reloc_t(o.D, base); reloc_t(o.e, base); reloc_t(o.cmax, base); reloc_t(o.status, base);
+  }
 }
 
 __global__ void relocate_oz_kernel(char* base, OzParams* z, int n) {
@@ -1440,6 +1531,10 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
                if (W.n_oz[r])
                  hipLaunchKernelGGL(relocate_oz_kernel, dim3((unsigned)cdiv(W.n_oz[r], 256)), dim3(256), 0, st, ws,
                                     (OzParams*)at(W.o_oz[r]), W.n_oz[r]);
+             for (int r = 0; r < Wave::kDigitLists; ++r)
+               if (W.n_dop[r])
+                 hipLaunchKernelGGL(relocate_digit_kernel, dim3((unsigned)cdiv(W.n_dop[r], 256)), dim3(256), 0, st,
+                                    ws, (DigitOp*)at(W.o_dop[r]), W.n_dop[r]);
              const int nc = W.win_oz[0] + W.win_oz[1];
              if (nc)
                hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(nc, 256)), dim3(256), 0, st,
@@ -1481,34 +1576,32 @@ int batch_run(rimp2_batch_s* B, int32_t* status_dev, void* workspace, size_t byt
     // per reduction window (r = 0: (ia|jb), r = 1: Gamma)
     auto run_split = [&](int r) -> int {
       int rc2;
-      for (int i = 0; i < n; ++i) {
-        const int32_t f = W.frags[i];
-        const rimp2_frag_desc& q = B->d[f];
-        const Plan& P = B->plan[f];
-        if (r == 1 && !P.gamma) continue;
-        char* fb = ws + W.base[i];
-        const int32_t* status = (const int32_t*)(fb + P.off_status);
-        const int64_t L = (int64_t)q.nocc * q.nvir, naux = q.naux;
-        if (r == 0) {
-          if ((rc2 = traced(R_SPLIT, 0, 0, 0, st, [&] {
-                 RIMP2_SWITCH_S(P.sv, launch_split_rows<SS>(q.B, L, naux, naux, (int8_t*)(fb + P.off_dbv), P.kpv,
-                                                            (int32_t*)(fb + P.off_ev), status, st));
-               })))
-            return rc2;
-        } else {
-          unsigned long long* cmax = (unsigned long long*)(fb + P.off_cmax);
-          const double* T = (const double*)(fb + P.off_T);
-          if ((rc2 = traced(R_SPLIT, 0, 0, 0, st, [&] {
-                 hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)cdiv(naux, 256)), dim3(256), 0, st, cmax, naux);
-                 hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cdiv(naux, 256), (unsigned)cdiv(L, 1024)), dim3(256),
-                                    0, st, q.B, L, naux, naux, cmax, status);
-                 RIMP2_SWITCH_S(P.sg, launch_split_cols<SS>(q.B, L, naux, naux, cmax, (int8_t*)(fb + P.off_dbg), P.kpg,
-                                                            (int32_t*)(fb + P.off_eg), status, st));
-                 RIMP2_SWITCH_S(P.sg, launch_split_rows<SS>(T, L, L, L, (int8_t*)(fb + P.off_dt), P.kpg,
-                                                            (int32_t*)(fb + P.off_et), status, st));
-               })))
-            return rc2;
-        }
+      // the digit splits of every fragment of the wave: one launch per list and mode
+      auto dlaunch = [&](int list, int mode, int S) -> int {
+        const int64_t blocks = W.blocks_dop[list][mode];
+        if (W.n_dop[list] == 0 || blocks == 0) return RIMP2_OK;
+        if (int rc3 = check_grid(blocks, "digit split")) return rc3;
+        const DigitOp* ops = (const DigitOp*)at(W.o_dop[list]);
+        const int64_t* pre = (const int64_t*)at(W.o_dpre[list][mode]);
+        return traced(R_SPLIT, 0, 0, 0, st, [&] {
+          switch (mode) {
+            case 0: RIMP2_SWITCH_S(S, hipLaunchKernelGGL((digit_split_grouped<SS, 0>), dim3((unsigned)blocks),
+                                                        dim3(256), 0, st, ops, pre, W.n_dop[list])); break;
+            case 1: hipLaunchKernelGGL((digit_split_grouped<1, 1>), dim3((unsigned)blocks), dim3(256), 0, st, ops,
+                                       pre, W.n_dop[list]); break;
+            case 2: hipLaunchKernelGGL((digit_split_grouped<1, 2>), dim3((unsigned)blocks), dim3(256), 0, st, ops,
+                                       pre, W.n_dop[list]); break;
+            default: RIMP2_SWITCH_S(S, hipLaunchKernelGGL((digit_split_grouped<SS, 3>), dim3((unsigned)blocks),
+                                                         dim3(256), 0, st, ops, pre, W.n_dop[list])); break;
+          }
+        });
+      };
+      const int sv = B->plan[W.frags[0]].sv, sg = B->plan[W.frags[0]].sg;
+      if (r == 0) {
+        if ((rc2 = dlaunch(0, 0, sv))) return rc2;
+      } else if ((rc2 = dlaunch(1, 1, sg)) || (rc2 = dlaunch(1, 2, sg)) || (rc2 = dlaunch(2, 3, sg)) ||
+                 (rc2 = dlaunch(3, 0, sg))) {
+        return rc2;
       }
       if (W.n_oz[r] == 0) return RIMP2_OK;
       const int S = r == 0 ? B->plan[W.frags[0]].sv : B->plan[W.frags[0]].sg;

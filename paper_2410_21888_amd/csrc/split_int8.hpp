@@ -31,10 +31,8 @@ constexpr int64_t kFlushK = 65536;
 // D[s][row][kp] (kp = K rounded up to 64, zero padded) and exps[row].
 // One workgroup per row.
 template <int S>
-__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_t rows, int64_t K, int64_t ld,
-                                                         int8_t* D, int64_t kp, int32_t* exps, const int32_t* status) {
-  if (status != nullptr && *status != 0) return;
-  const int64_t row = blockIdx.x;
+__device__ __forceinline__ void split_row(const double* X, int64_t rows, int64_t K, int64_t ld, int8_t* D,
+                                          int64_t kp, int32_t* exps, int64_t row) {
   const double* x = X + row * ld;
   __shared__ double sm[256];
   double mx = 0.0;
@@ -59,29 +57,40 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_
   }
 }
 
+template <int S>
+__global__ __launch_bounds__(256) void split_rows_kernel(const double* X, int64_t rows, int64_t K, int64_t ld,
+                                                         int8_t* D, int64_t kp, int32_t* exps, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  split_row<S>(X, rows, K, ld, D, kp, exps, blockIdx.x);
+}
+
 // Column maxima of X[K][N] (row stride ld) as IEEE bit patterns (non-negative
 // doubles order like their bit patterns, so an integer max is exact and
 // order-independent).  cmax must start at zero.
-__global__ __launch_bounds__(256) void colmax_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
-                                                     unsigned long long* cmax, const int32_t* status) {
-  if (status != nullptr && *status != 0) return;
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void colmax_block(const double* X, int64_t K, int64_t N, int64_t ld,
+                                             unsigned long long* cmax, int64_t bx, int64_t by) {
+  const int64_t n = bx * 256 + threadIdx.x;
   if (n >= N) return;
-  const int64_t k0 = (int64_t)blockIdx.y * 1024, k1 = min(K, k0 + 1024);
+  const int64_t k0 = by * 1024, k1 = min(K, k0 + 1024);
   double mx = 0.0;
   for (int64_t k = k0; k < k1; ++k) mx = fmax(mx, fabs(X[k * ld + n]));
   atomicMax(cmax + n, (unsigned long long)__double_as_longlong(mx));
 }
 
+__global__ __launch_bounds__(256) void colmax_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
+                                                     unsigned long long* cmax, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  colmax_block(X, K, N, ld, cmax, blockIdx.x, blockIdx.y);
+}
+
 // Column-scaled digits of X[K][N], written transposed: D[s][n][kp], exps[n].
 // 32 x 32 tiles through LDS so both the read and the write are coalesced.
 template <int S>
-__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
-                                                         const unsigned long long* cmax, int8_t* D, int64_t kp,
-                                                         int32_t* exps, const int32_t* status) {
-  if (status != nullptr && *status != 0) return;
+__device__ __forceinline__ void split_cols_tile(const double* X, int64_t K, int64_t N, int64_t ld,
+                                                const unsigned long long* cmax, int8_t* D, int64_t kp,
+                                                int32_t* exps, int64_t bx, int64_t by) {
   __shared__ double tile[32][33];
-  const int64_t k0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+  const int64_t k0 = bx * 32, n0 = by * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -104,6 +113,14 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_
       y = (y - d) * 128.0;
     }
   }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void split_cols_kernel(const double* X, int64_t K, int64_t N, int64_t ld,
+                                                         const unsigned long long* cmax, int8_t* D, int64_t kp,
+                                                         int32_t* exps, const int32_t* status) {
+  if (status != nullptr && *status != 0) return;
+  split_cols_tile<S>(X, K, N, ld, cmax, D, kp, exps, blockIdx.x, blockIdx.y);
 }
 
 struct OzParams {
