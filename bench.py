@@ -554,7 +554,9 @@ def bench_mbe3(args, torch, synth, rm, dev):
                           P_ij=torch.empty((F.nocc, F.nocc), **f64), P_ab=torch.empty((F.nvir, F.nvir), **f64),
                           e_pair=torch.empty((F.nocc, F.nocc), **f64)))
         total_alg += rm.flops(F.nocc, F.nvir, F.naux)["algorithmic"]
-    batch = rm.Batch(frags)
+    # --mbe3-batch-only --precision split: the grouped split-precision batch alone
+    split_only = args.mbe3_batch_only and args.precision == "split"
+    batch = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8) if split_only else None)
     ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device=dev)
     status = torch.zeros(len(frags), dtype=torch.int32, device=dev)
 
@@ -601,10 +603,12 @@ def bench_mbe3(args, torch, synth, rm, dev):
         print(json.dumps({
             "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "mbe3 batch (grouped batch only): %d of the 4096 recipe fragments (every %d-th, "
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "int8 digit products (Ozaki), f64 elsewhere" if split_only else "f64", "data": "synthetic",
+            "config": {"workload": "mbe3 batch (grouped %sbatch only): %d of the 4096 recipe fragments (every %d-th, "
                                    "orders %s): %d monomers, %d dimers, %d trimers"
-                                   % (len(ids), args.mbe3_stride, args.mbe3_kinds, kinds[1], kinds[2], kinds[3]),
+                                   % ("split-precision " if split_only else "", len(ids), args.mbe3_stride,
+                                      args.mbe3_kinds, kinds[1], kinds[2], kinds[3]),
                        "fragments": len(ids), "flops_counted": "algorithmic E+Gamma+P_ab+P_ij"},
             "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4), "sampled_parity": sampled,
             "kernels": {st["name"]: {"launches": st["launches"], "ms": round(st["total_ms"] / args.steps, 2)}
