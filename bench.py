@@ -631,13 +631,14 @@ def bench_mbe3(args, torch, synth, rm, dev):
     print("[bench] graph replay %.3f s" % t_graph, file=sys.stderr, flush=True)
     # one call per fragment (largest first), each with its own default plan
     order = sorted(range(len(frags)), key=lambda i: -frags[i]["B"].numel() * frags[i]["B"].shape[0])
-    ws1 = torch.empty(max(rm.workspace_size(*frags[i]["B"].shape) for i in order), dtype=torch.uint8, device=dev)
+    n_ws1 = max(rm.workspace_size(*frags[i]["B"].shape) for i in order)
+    ws1 = [torch.empty(n_ws1, dtype=torch.uint8, device=dev)]   # released while the split batch runs
 
     def loop(opts=None):
         for i in order:
             d = frags[i]
             rm.fragment_into(d["B"], d["eps_occ"], d["eps_vir"], d["E"], d["Gamma"], d["P_ij"], d["P_ab"],
-                             d["e_pair"], workspace=ws1, opts=opts)
+                             d["e_pair"], workspace=ws1[0], opts=opts)
     loop()
     t_loop = timed(loop, args.steps)
     print("[bench] per-fragment loop %.3f s" % t_loop, file=sys.stderr, flush=True)
@@ -645,6 +646,8 @@ def bench_mbe3(args, torch, synth, rm, dev):
     dE = float((E_loop - E_batch).abs().max())
     split = None
     if args.precision == "split":   # grouped split products for (ia|jb) and Gamma
+        ws1[0] = None
+        torch.cuda.empty_cache()
         sb = rm.Batch(frags, opts=rm.make_opts(precision=rm.SPLIT_INT8))
         ws_s = torch.empty(sb.workspace_bytes, dtype=torch.uint8, device=dev)
         sb.run(ws_s, status)
@@ -658,6 +661,8 @@ def bench_mbe3(args, torch, synth, rm, dev):
                    for a, b in zip(E_s.cpu().numpy(), E_batch.cpu().numpy()))
         sb.close()
         del ws_s
+        torch.cuda.empty_cache()
+        ws1[0] = torch.empty(n_ws1, dtype=torch.uint8, device=dev)
         split = {"split_batch_tflops": round(total_alg / t_split / 1e12, 4),
                  "speedup_split_vs_fp64_batch": round(t_batch / t_split, 4), "max_abs_dE_vs_fp64_Eh": dE_s,
                  "kernels": {x["name"]: {"launches": x["launches"], "ms": round(x["total_ms"] / args.steps, 2)}

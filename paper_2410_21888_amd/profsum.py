@@ -98,6 +98,7 @@ def role_of(name: str) -> str:
                       ("splitk_reduce", "splitk_reduce"), ("reduce_grouped", "splitk_reduce"),
                       ("energy_sum", "energy_sum"), ("gap_check", "gap_check"), ("split_rows", "digit_split"),
                       ("split_cols", "digit_split"), ("colmax", "digit_split"), ("zero_u64", "digit_split"),
+                      ("digit_split_grouped", "digit_split"), ("relocate_digit", "status_copy"),
                       ("copy_status", "status_copy"), ("status_copy", "status_copy"),
                       ("relocate_tables", "status_copy"), ("relocate_oz", "status_copy"),
                       ("zero_counters", "status_copy"),

@@ -30,6 +30,7 @@ def test_roles_of_kernel_symbols():
     assert profsum.role_of("__amd_rocclr_copyBuffer") == "(runtime copy)"
     assert profsum.role_of("void rimp2::gemm_oz8_kernel<7, 1>(rimp2::OzParams)") == "oz8 S=7"
     assert profsum.role_of("void rimp2::gemm_oz8_grouped<5, 2>(rimp2::OzGroup, long, long)") == "oz8 S=5 (grouped)"
+    assert profsum.role_of("void (anonymous namespace)::digit_split_grouped<5, 0>(DigitOp const*)") == "digit_split"
 
 
 def test_traffic_scales_by_the_calibration_copy(tmp_path):
