@@ -18,6 +18,8 @@ whole path, on ordered pairs).  Prints one JSON line.
   split_e_gamma  (FP64 E+Gamma line) the same E+Gamma step with split-precision
              INT8 products, its speedup over the FP64 step and its differences
              from the FP64 result
+  digit_sweep  (--digit-sweep) the split E+Gamma step once per digit count,
+             each with its speedup and its differences from the FP64 result
   cpu_baseline  the CPU oracle on one occupied slab (k = 0) of the same
              workload, i.e. 1/nocc of the job, timed on this host's cores
 
@@ -186,6 +188,10 @@ def main():
                          "symmetric path; the default), all = also P_ij and P_ab (the whole path, ordered pairs)")
     ap.add_argument("--no-split-sub", action="store_true",
                     help="large, FP64, E+Gamma: skip the split-precision E+Gamma step after the timed steps")
+    ap.add_argument("--digit-sweep", action="store_true",
+                    help="large, FP64, E+Gamma: after the timed steps run the split-precision E+Gamma step once per "
+                         "digit count ((ia|jb) 3..7 digits with Gamma at 5, Gamma 3..7 with (ia|jb) at 7) and "
+                         "report each one's time and differences from the FP64 result (digit_sweep)")
     ap.add_argument("--no-sub", "--no-e-gamma", dest="no_sub", action="store_true",
                     help="large: skip the sub-record (the same fragment in the other --outputs form)")
     ap.add_argument("--autotune", action="store_true",
@@ -251,9 +257,14 @@ def bench_large(args, torch, synth, rm, dev):
     need_eg = eg_main or not args.no_sub
     split_sub = eg_main and args.precision == "fp64" and not args.no_split_sub
     opts_split = rm.make_opts(slab_group=args.slab_group, precision=rm.SPLIT_INT8) if split_sub else None
-    ws = torch.empty(max(rm.workspace_size(nocc, nvir, naux, True, True, opts) if need_full else 0,
-                         rm.workspace_size(nocc, nvir, naux, True, False, opts) if need_eg else 0,
-                         rm.workspace_size(nocc, nvir, naux, True, False, opts_split) if split_sub else 0),
+    sweep = eg_main and args.precision == "fp64" and args.digit_sweep
+    sweep_pts = ([(sv, 5) for sv in range(3, 8)] + [(7, sg) for sg in (3, 4, 6, 7)]) if sweep else []
+    sweep_opts = [rm.make_opts(slab_group=args.slab_group, precision=rm.SPLIT_INT8, split_slices=sv,
+                               split_slices_gamma=sg) for sv, sg in sweep_pts]
+    ws = torch.empty(max([rm.workspace_size(nocc, nvir, naux, True, True, opts) if need_full else 0,
+                          rm.workspace_size(nocc, nvir, naux, True, False, opts) if need_eg else 0,
+                          rm.workspace_size(nocc, nvir, naux, True, False, opts_split) if split_sub else 0] +
+                         [rm.workspace_size(nocc, nvir, naux, True, False, o) for o in sweep_opts]),
                      dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -289,6 +300,8 @@ def bench_large(args, torch, synth, rm, dev):
         reserve += 2.0 * 0.7 * step_s + 10.0
     if args.compare_fp64:
         reserve += 1.2 * step_s
+    if sweep:       # about 0.5-0.9 of an FP64 E+Gamma step per point, plus a warm call
+        reserve += 0.8 * step_s * (len(sweep_pts) + 1)
     if cold:
         warmup, steps = 0, 1
     else:
@@ -457,6 +470,45 @@ def bench_large(args, torch, synth, rm, dev):
         ep.copy_(ep64)
         del G64, ep64
         log("split E+Gamma step: %.2f s (%.3fx the FP64 step)" % (ts, dt / ts))
+
+    # digit-count sweep of the split E+Gamma step against this run's FP64
+    # E+Gamma result (one warm call at the first point, then one timed call per
+    # point; points that do not fit the budget are left out)
+    if sweep:
+        G64, ep64 = G.clone(), ep.clone()
+        ep64_np = ep64.cpu().numpy()
+        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        pts = []
+        rm.fragment_into(B, deo, dev_, E, G, None, None, ep, workspace=ws, opts=sweep_opts[-1])
+        torch.cuda.synchronize()
+        for (sv, sg), o in zip(sweep_pts, sweep_opts):
+            if left() < 1.1 * step_s + cpu_est:
+                log("digit sweep: no time left for ints=%d gamma=%d" % (sv, sg))
+                break
+            t2 = time.perf_counter()
+            rm.fragment_into(B, deo, dev_, E, G, None, None, ep, workspace=ws, opts=o)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t2
+            if rm.read_status(ws) != rm.RIMP2_OK:
+                raise SystemExit("device status not OK in the digit sweep")
+            E_s = E.cpu().numpy().copy()
+            dE = abs(math.fsum([float(E_s[0]), float(E_s[1]), -float(E_main[0]), -float(E_main[1])]))
+            ep_np = ep.cpu().numpy()
+            pts.append({"ints_digits": sv, "gamma_digits": sg, "ms_per_step": round(ts * 1e3, 3),
+                        "speedup_vs_fp64": round(dt / ts, 4), "abs_dE_vs_fp64_Eh": dE,
+                        "gamma_rel_fro_vs_fp64": rel(G, G64), "e_pair_rel_fro_vs_fp64": rel(ep, ep64),
+                        "e_pair_max_abs_vs_fp64_Eh": float(np.max(np.abs(ep_np - ep64_np))),
+                        "within_tolerances": bool(dE <= 1e-6 and rel(G, G64) <= 1e-8)})
+            log("digit sweep ints=%d gamma=%d: %.2f s (%.3fx), |dE| = %.3g Eh, Gamma %.3g"
+                % (sv, sg, ts, dt / ts, dE, pts[-1]["gamma_rel_fro_vs_fp64"]))
+        ok = [q for q in pts if q["within_tolerances"]]
+        out["digit_sweep"] = {"points": pts, "tolerances": "|dE| <= 1e-6 Eh and Gamma relative Frobenius <= 1e-8 "
+                                                           "against this run's FP64 E+Gamma step",
+                              "fastest_within_tolerances": (max(ok, key=lambda q: q["speedup_vs_fp64"])
+                                                            if ok else None)}
+        G.copy_(G64)
+        ep.copy_(ep64)
+        del G64, ep64
 
     # the sub-record: the same fragment in the other form (the whole path when
     # the main record is E+Gamma, E+Gamma alone otherwise), timed the same way
