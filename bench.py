@@ -69,13 +69,20 @@ def measured_traffic(role: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(B, eo, ev, nocc, alg_total, sample_slabs, density=True):
-    from oracle import rimp2_oracle as O
+def blas_cores() -> int:
     try:
         from threadpoolctl import threadpool_info
-        cores = sum(p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas") or os.cpu_count()
+        return int(sum(p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas")
+                   or os.cpu_count())
     except Exception:
-        cores = os.cpu_count()
+        return int(os.cpu_count())
+
+
+def cpu_baseline(B, eo, ev, nocc, alg_total, sample_slabs, density=True):
+    """The CPU oracle on some occupied slabs of one fragment: its outputs (the
+    references of the sampled parity checks) and the baseline record."""
+    from oracle import rimp2_oracle as O
+    cores = blas_cores()
     t0 = time.perf_counter()
     ref = O.fragment(B, eo, ev, density=density, slabs=sample_slabs)
     dt = time.perf_counter() - t0
@@ -84,6 +91,35 @@ def cpu_baseline(B, eo, ev, nocc, alg_total, sample_slabs, density=True):
                  "sample": "occupied slab(s) %s of %d (all pairs (k,j), Gamma rows k%s); %.3g algorithmic FLOP "
                            "(the slabs' share of the job's) in %.1f s"
                            % (list(sample_slabs), nocc, ", their P_ab/P_ij terms" if density else "", flops, dt)}
+
+
+def cpu_baseline_fragments(arrays, alg_flops):
+    """The CPU oracle on whole fragments (arrays: (B, eps_occ, eps_vir) per
+    fragment, alg_flops: each one's algorithmic FLOPs): the references and the
+    baseline record."""
+    from oracle import rimp2_oracle as O
+    t0 = time.perf_counter()
+    refs = [O.fragment(B, eo, ev) for B, eo, ev in arrays]
+    dt = time.perf_counter() - t0
+    flops = float(sum(alg_flops))
+    return refs, {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": blas_cores(), "kind": "oracle",
+                  "sample": "%d whole fragments (nocc %s; E, e_ij, Gamma, P_ij, P_ab); %.3g algorithmic FLOP in %.3g s"
+                            % (len(arrays), [int(a[0].shape[0]) for a in arrays], flops, dt)}
+
+
+def cpu_baseline_pairs(B, eo, ev, pairs):
+    """The CPU oracle's pair energies e_ij for some occupied pairs of one
+    fragment (each pair's (ia|jb) block: 2 nvir^2 naux FLOP, its share of the
+    symmetric count): the references and the baseline record."""
+    from oracle import rimp2_oracle as O
+    nvir, naux = B.shape[1], B.shape[2]
+    t0 = time.perf_counter()
+    refs = [float(O.pair_energy(B, eo, ev, i, j)) for i, j in pairs]
+    dt = time.perf_counter() - t0
+    flops = 2.0 * nvir * nvir * naux * len(pairs)
+    return refs, {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": blas_cores(), "kind": "oracle",
+                  "sample": "pair energies of %d occupied pairs (their share of the energy-only count); %.3g "
+                            "algorithmic FLOP in %.3g s" % (len(pairs), flops, dt)}
 
 
 def plan_steps(req_steps: int, req_warmup: int, budget_s: float, elapsed_s: float, step_s: float,
@@ -629,14 +665,20 @@ def bench_mbe3(args, torch, synth, rm, dev):
     # sampled parity in the timed launch configuration: the smallest, a middle
     # and the largest fragment of at most 40 occupied orbitals, against the
     # CPU oracle on the device's own B (read back)
-    sampled = []
+    sampled, cb = [], None
     if not args.no_cpu_baseline:
-        from oracle import rimp2_oracle as O
         cand = sorted((i for i in range(len(frags)) if frags[i]["B"].shape[0] <= 40),
                       key=lambda i: frags[i]["B"].shape[0])
-        for i in sorted({cand[0], cand[len(cand) // 2], cand[-1]} if cand else set()):
+        picks = sorted({cand[0], cand[len(cand) // 2], cand[-1]} if cand else set())
+        arrays = [(frags[i]["B"].cpu().numpy(), frags[i]["eps_occ"].cpu().numpy(), frags[i]["eps_vir"].cpu().numpy())
+                  for i in picks]
+        refs = []
+        if arrays:
+            refs, cb = cpu_baseline_fragments(
+                arrays, [rm.flops(*a[0].shape, gamma=True, density=True)["algorithmic"] for a in arrays])
+        del arrays
+        for i, ref in zip(picks, refs):
             d = frags[i]
-            ref = O.fragment(d["B"].cpu().numpy(), d["eps_occ"].cpu().numpy(), d["eps_vir"].cpu().numpy())
             e = E_batch[i].cpu().numpy()
             g = d["Gamma"].cpu().numpy()
             sampled.append({"nocc": int(d["B"].shape[0]),
@@ -662,7 +704,7 @@ def bench_mbe3(args, torch, synth, rm, dev):
                                    % ("split-precision " if split_only else "", len(ids), args.mbe3_stride,
                                       args.mbe3_kinds, kinds[1], kinds[2], kinds[3]),
                        "fragments": len(ids), "flops_counted": "algorithmic E+Gamma+P_ab+P_ij"},
-            "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4), "sampled_parity": sampled,
+            "frac_fp64_peak": round(value / FP64_PEAK_TFLOPS, 4), "sampled_parity": sampled, "cpu_baseline": cb,
             "kernels": {st["name"]: {"launches": st["launches"], "ms": round(st["total_ms"] / args.steps, 2)}
                         for st in sorted(stats, key=lambda x: -x["total_ms"])},
             "roofline": {"bound": "mfma", "kernel": max(gemm, key=lambda x: x["total_ms"])["name"] + " (grouped)",
@@ -787,6 +829,7 @@ def bench_mbe3(args, torch, synth, rm, dev):
                      "chosen_tiles": decisions},
         "max_abs_dE_batch_vs_loop_Eh": dE,
         "sampled_parity": sampled,
+        "cpu_baseline": cb,
         "split": split,
         "roofline": {"bound": "mfma", "kernel": dom["name"] + " (grouped)", "achieved": None, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": None, "traffic": None,
@@ -951,8 +994,8 @@ def bench_screen(args, torch, synth, rm, dev):
     ep0 = e_pair.cpu().numpy().copy()
     E0 = E.cpu().numpy().copy()
     # sampled parity at full size, in the launch configuration timed: e_ij of
-    # 6 pairs (near, middle and far) against the oracle on the device's own B
-    from oracle import rimp2_oracle as O
+    # 6 pairs (near, middle and far) against the CPU baseline's oracle run on
+    # the device's own B
     B_np = B.cpu().numpy()
     eo_np, ev_np = eo.cpu().numpy(), ev.cpu().numpy()
     dist = np.sqrt(((r[:, None, :] - r[None, :, :]) ** 2).sum(-1))
@@ -961,10 +1004,10 @@ def bench_screen(args, torch, synth, rm, dev):
     picks = [order_d[0], order_d[len(order_d) // 3], order_d[len(order_d) // 2], order_d[2 * len(order_d) // 3],
              order_d[-1]]
     pair_checks = [(0, 0)] + [(int(iu_all[0][q]), int(iu_all[1][q])) for q in picks]
-    max_rel_pair = 0.0
-    for (pi_, pj_) in pair_checks:
-        ref_e = float(O.pair_energy(B_np, eo_np, ev_np, pi_, pj_))
-        max_rel_pair = max(max_rel_pair, abs(ep0[pi_, pj_] - ref_e) / abs(ref_e))
+    max_rel_pair, cb = None, None
+    if not args.no_cpu_baseline:
+        refs, cb = cpu_baseline_pairs(B_np, eo_np, ev_np, pair_checks)
+        max_rel_pair = max(abs(ep0[pi_, pj_] - ref_e) / abs(ref_e) for (pi_, pj_), ref_e in zip(pair_checks, refs))
     del B_np
     off = ~np.eye(nocc, dtype=bool)
     ptrue = np.log10(np.maximum(-ep0[iu], 1e-300))
@@ -1029,6 +1072,7 @@ def bench_screen(args, torch, synth, rm, dev):
                   "saved_to": args.screen_save or None},
         "E_unscreened": [float(E0[0]), float(E0[1])],
         "sampled_parity": {"pairs": pair_checks, "e_pair_max_rel": max_rel_pair},
+        "cpu_baseline": cb,
     }
     # roofline of the unscreened run's dominant kernel (HIP events around each launch)
     dom = max(st0, key=lambda x: x["total_ms"])

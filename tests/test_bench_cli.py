@@ -58,3 +58,24 @@ def test_planner_prefers_timed_steps_over_extra_warmup():
     # room for 6 with 4 requested: the other 2 become warmup steps
     warmup, steps = bench.plan_steps(4, 5, 420.0, 60.0, 50.0, 45.0)
     assert steps == 4 and warmup == 3
+
+
+def test_cpu_baseline_legs_return_the_oracle_and_a_rate():
+    """The MBE3 and screening CPU baselines time the oracle on whole fragments
+    and on single pair energies; their outputs are the oracle's own (the
+    references of the sampled parity checks)."""
+    import numpy as np
+    import synth
+    from oracle import rimp2_oracle as O
+    import paper_2410_21888_amd as rm
+    f = synth.random_fragment(3, 10, 24, seed=5)
+    B, eo, ev = f.arrays()
+    refs, cb = bench.cpu_baseline_fragments([(B, eo, ev)], [rm.flops(3, 10, 24, gamma=True, density=True)["algorithmic"]])
+    ref = O.fragment(B, eo, ev)
+    assert refs[0]["E_hi"] == ref["E_hi"] and np.array_equal(refs[0]["Gamma"], ref["Gamma"])
+    assert cb["kind"] == "oracle" and cb["unit"] == "TFLOP/s" and cb["value"] > 0 and cb["cores"] >= 1
+    pairs = [(0, 0), (0, 2)]
+    prefs, pcb = bench.cpu_baseline_pairs(B, eo, ev, pairs)
+    assert prefs == [float(O.pair_energy(B, eo, ev, i, j)) for i, j in pairs]
+    assert prefs[1] == ref["e_pair"][0, 2] or abs(prefs[1] - ref["e_pair"][0, 2]) <= 1e-12 * abs(ref["e_pair"][0, 2])
+    assert pcb["value"] > 0 and "2 occupied pairs" in pcb["sample"]
