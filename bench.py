@@ -22,6 +22,9 @@ whole path, on ordered pairs).  Prints one JSON line.
              each with its speedup and its differences from the FP64 result
   cpu_baseline  the CPU oracle on one occupied slab (k = 0) of the same
              workload, i.e. 1/nocc of the job, timed on this host's cores
+             (--workload mbe3: three whole fragments of the batch; --workload
+             screen: six pair energies); its outputs are the references of
+             the line's sampled parity checks
 
 A step of the large fragment takes tens of seconds, so the run keeps to a
 wall-clock budget (--budget-s, from process start): the first step is always
