@@ -297,6 +297,8 @@ def bench_large(args, torch, synth, rm, dev):
     split_sub = eg_main and args.precision == "fp64" and not args.no_split_sub
     opts_split = rm.make_opts(slab_group=args.slab_group, precision=rm.SPLIT_INT8) if split_sub else None
     sweep = eg_main and args.precision == "fp64" and args.digit_sweep
+    if args.digit_sweep and not sweep:
+        log("--digit-sweep runs with the FP64 E+Gamma line only (--precision fp64 --outputs eg): not run")
     sweep_pts = ([(sv, 5) for sv in range(3, 8)] + [(7, sg) for sg in (3, 4, 6, 7)]) if sweep else []
     sweep_opts = [rm.make_opts(slab_group=args.slab_group, precision=rm.SPLIT_INT8, split_slices=sv,
                                split_slices_gamma=sg) for sv, sg in sweep_pts]
